@@ -1,0 +1,106 @@
+"""Analytic FP64 gradient of the oracle's per-ray render.
+
+The paper optimises site positions, density parameters and both texture maps
+with Adam (Sec. 5.5) but prints no adjoint; this is the plain chain rule of
+the forward model in ``render`` (Sec. 3.2 compositing, Sec. 3.1 bisector
+crossings), written term by term:
+
+Compositing.  With tau_k = sigma_k delta_k, T_k = exp(-sum_{j<k} tau_j) and
+w_k = T_k - T_{k+1}:
+    dC/dtau_k       = T_{k+1} c_k - sum_{j>k} w_j c_j
+    dT_final/dtau_k = -T_final
+    dC/dc_k         = w_k
+so for L = g . C + g_T T_final:
+    dL/dtau_k = g . (T_{k+1} c_k - S_k) - g_T T_final,   S_k = sum_{j>k} w_j c_j
+    dL/dsigma_{i_k} += dL/dtau_k * delta_k
+    dL/dtexel_q     += w_k * b_q * g      (b_q: bilinear weight of tap q)
+
+Segment ends.  delta_k = t_exit - t_entry (when positive).  Its exit end is
+the bisector crossing out of i_k unless clipped at tmax; its entry end is the
+crossing that last advanced t (none for the first segment).  Each end moves
+with the sites: for the bisector of (a, b) crossed at t, with n = p_b - p_a,
+beta = n . w and x = o + t w,
+    dt/dp_b = (p_b - x) / beta,   dt/dp_a = (x - p_a) / beta.
+Stopping decisions, the start cell and the cell sequence are piecewise
+constant: no gradient flows through tmax, early termination or max_steps.
+
+Under sigma = exp(rho) (Sec. 5.4) the caller's autograd multiplies by sigma,
+giving dL/drho = dL/dalpha (1 - alpha) ln(1/(1 - alpha)) per segment.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import appearance, walk
+
+
+def face_dt_dsites(sites, a, b, o, w, t):
+    """(dt/dp_a, dt/dp_b) for the bisector of sites a, b crossed at parameter t."""
+    p = walk.as64(sites)
+    o = walk.as64(o)
+    w = walk.as64(w)
+    n = p[b] - p[a]
+    beta = float(n @ w)
+    x = o + t * w
+    return (x - p[a]) / beta, (p[b] - x) / beta
+
+
+def grad_ray(sites, density, texels, o, w, tmax, rec, g_rgb, g_T, g_sites, g_density,
+             g_texels):
+    """Accumulate dL/d(sites, density, texels) of one ray into the dense arrays.
+
+    ``rec`` is the oracle forward record of this ray (render.render_ray).
+    """
+    sig = walk.as64(density)
+    g = np.asarray(g_rgb, np.float64)
+    gT = float(g_T)
+    w = walk.as64(w)
+    res = texels.shape[1]
+    C = np.asarray(rec.rgb, np.float64)
+    Tf = float(rec.T)
+    K = rec.K
+    taps = appearance.bilinear_weights(w, res)
+    # suffix sums S_k = C - sum_{j<=k} w_j c_j
+    prefix = np.zeros(3)
+    entry_face = None  # (a, b, t) of the crossing that set the current entry
+    for k in range(K):
+        i = rec.cells[k]
+        wk = rec.weight[k]
+        ck = rec.color[k]
+        prefix = prefix + wk * ck
+        S = C - prefix
+        T_next = rec.T_before[k] * np.exp(-sig[i] * rec.delta[k])
+        dtau = float(g @ (T_next * ck - S)) - gT * Tf
+        g_density[i] += dtau * rec.delta[k]
+        if not rec.skipped[k]:
+            for r, col, bw in taps:
+                g_texels[i, r, col, :3] += wk * bw * g
+        if rec.delta[k] > 0.0:
+            ddelta = sig[i] * dtau
+            if entry_face is not None:
+                a, b, t = entry_face
+                da, db = face_dt_dsites(sites, a, b, o, w, t)
+                g_sites[a] -= ddelta * da
+                g_sites[b] -= ddelta * db
+            ex = rec.exit[k]
+            if ex < tmax and rec.nxt[k] >= 0:
+                da, db = face_dt_dsites(sites, i, rec.nxt[k], o, w, ex)
+                g_sites[i] += ddelta * da
+                g_sites[rec.nxt[k]] += ddelta * db
+                entry_face = (i, rec.nxt[k], ex)
+
+
+def grad_rays(sites, density, texels, origins, dirs, tmax, recs, g_rgb, g_T):
+    """Dense FP64 gradients summed over rays: (g_sites[N,3], g_density[N], g_texels[N,R,R,4])."""
+    N = len(sites)
+    res = texels.shape[1]
+    gs = np.zeros((N, 3))
+    gd = np.zeros(N)
+    gt = np.zeros((N, res, res, 4))
+    tm = np.broadcast_to(np.asarray(tmax, np.float64), (len(origins),))
+    for r, rec in enumerate(recs):
+        if rec is None:
+            continue
+        grad_ray(sites, density, texels, origins[r], dirs[r], tm[r], rec, g_rgb[r], g_T[r],
+                 gs, gd, gt)
+    return gs, gd, gt

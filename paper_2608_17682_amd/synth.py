@@ -1,0 +1,316 @@
+"""Seeded synthetic scenes, cameras and upstream gradients.
+
+This module only *draws inputs*: site positions, per-cell densities, texels,
+camera descriptions (pose and lens parameters) and upstream gradients.  It
+holds none of the rendering arithmetic (no ray generation, no walk, no
+compositing), so both the FP64 oracle and the HIP path can be fed from it.
+
+The Delaunay adjacency (the walk's only topology, Sec. 3.1 "Adjacency-Based
+Traversal") is built here with scipy's Qhull as an input to the GPU path; the
+oracle never reads it, it only validates it.
+
+Scenes stand in for the paper's trained Mip-NeRF 360 models (Sec. 6.1), which
+are not available: the shapes follow the paper's 2M-site budget (Sec. 5.5),
+~1 Mpix views and surface-concentrated, bimodal opacity (Sec. 5.3).
+Random draws use ``numpy.random.default_rng(config_no)`` in the order
+sites -> density -> texels -> cameras -> upstream gradients.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+# camera models (same numbering as the C ABI's voro_camera.model)
+PINHOLE = 0
+FISHEYE = 1          # equidistant fisheye, theta = r / f
+ROLLING_SHUTTER = 2  # per-row camera centre c0 + s * delta, s = row / (H - 1)
+THIN_LENS = 3        # depth of field, spp aperture samples per pixel
+
+
+@dataclasses.dataclass
+class Scene:
+    sites: np.ndarray      # [N,3] float32
+    density: np.ndarray    # [N]   float32 (sigma, not rho)
+    texels: np.ndarray     # [N,R,R,4] float32, RGBA with A = 0 (row = v, col = u)
+    nbr_off: np.ndarray    # [N+1] int32 CSR offsets (Delaunay adjacency)
+    nbr_idx: np.ndarray    # [M]   int32 CSR neighbour ids
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.sites.shape[0])
+
+    @property
+    def tex_res(self) -> int:
+        return int(self.texels.shape[1])
+
+
+@dataclasses.dataclass
+class Camera:
+    """A camera *description*; rays are generated from it by each side."""
+    model: int
+    width: int
+    height: int
+    c2w: np.ndarray            # [3,4] float64: columns = right, down, forward, centre
+    fov: float                 # radians; pinhole: horizontal FOV, fisheye: full FOV
+    tmax: float
+    rs_delta: tuple = (0.0, 0.0, 0.0)   # rolling shutter: world-space centre shift over the frame
+    lens_radius: float = 0.0           # thin lens
+    focus_dist: float = 1.0            # thin lens, along the optical axis
+    spp: int = 1                       # thin lens samples per pixel (a square number)
+
+    @property
+    def n_pixels(self) -> int:
+        return self.width * self.height
+
+    @property
+    def n_rays(self) -> int:
+        return self.width * self.height * self.spp
+
+
+def look_at(centre, target, up=(0.0, 1.0, 0.0)) -> np.ndarray:
+    """Camera-to-world [3,4] with OpenCV axes (+x right, +y down, +z forward)."""
+    c = np.asarray(centre, np.float64)
+    f = np.asarray(target, np.float64) - c
+    f /= np.linalg.norm(f)
+    upv = np.asarray(up, np.float64)
+    if abs(float(np.dot(f, upv))) > 0.999:
+        upv = np.array([0.0, 0.0, 1.0])
+    x = np.cross(f, upv)
+    x /= np.linalg.norm(x)
+    y = np.cross(f, x)
+    m = np.zeros((3, 4))
+    m[:, 0], m[:, 1], m[:, 2], m[:, 3] = x, y, f, c
+    return m
+
+
+def orbit_pose(angle: float, radius: float = 3.0) -> np.ndarray:
+    """Pose on a circle in the xz-plane looking at the origin."""
+    c = (radius * math.sin(angle), 0.0, -radius * math.cos(angle))
+    return look_at(c, (0.0, 0.0, 0.0))
+
+
+# ----------------------------------------------------------------- adjacency
+
+def delaunay_csr(sites: np.ndarray):
+    """Symmetric Delaunay adjacency of the sites as CSR (int32 offsets, ids).
+
+    Rows are sorted by neighbour id.  Built with scipy's Qhull on the CPU.
+    """
+    from scipy.spatial import Delaunay
+    pts = np.asarray(sites, np.float64)
+    tri = Delaunay(pts)
+    indptr, indices = tri.vertex_neighbor_vertices
+    off = np.asarray(indptr, np.int64)
+    idx = np.asarray(indices, np.int64)
+    # sort each row (Qhull order is arbitrary)
+    row = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    order = np.lexsort((idx, row))
+    idx = idx[order]
+    if off[-1] >= 2**31:
+        raise ValueError("adjacency too large for int32 offsets")
+    return off.astype(np.int32), idx.astype(np.int32)
+
+
+def _texels(rng, n, res):
+    tex = np.zeros((n, res, res, 4), np.float32)
+    tex[..., :3] = rng.uniform(0.0, 1.0, (n, res, res, 3)).astype(np.float32)
+    return tex
+
+
+def _unit_shell(rng, n, jitter=0.01):
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v + rng.normal(scale=jitter, size=(n, 3))
+
+
+# -------------------------------------------------------------------- configs
+
+def scene_uniform(n=512, tex_res=4, seed=1, with_csr=True) -> Scene:
+    """Config 1: uniform sites in [-1,1]^3, sigma = exp(N(0,1)), U[0,1] texels."""
+    rng = np.random.default_rng(seed)
+    sites = rng.uniform(-1.0, 1.0, (n, 3)).astype(np.float32)
+    density = np.exp(rng.normal(0.0, 1.0, n)).astype(np.float32)
+    tex = _texels(rng, n, tex_res)
+    off, idx = delaunay_csr(sites) if with_csr else (None, None)
+    return Scene(sites, density, tex, off, idx, name=f"uniform{n}")
+
+
+def scene_shell(n=100_000, tex_res=8, seed=2, shell_frac=0.7, with_csr=True) -> Scene:
+    """Config 2 (and 4/5 structure): jittered unit-sphere shell + uniform background.
+
+    Density 50 on the shell, 0.01 elsewhere.
+    """
+    rng = np.random.default_rng(seed)
+    n_shell = int(round(n * shell_frac))
+    shell = _unit_shell(rng, n_shell)
+    bg = rng.uniform(-2.0, 2.0, (n - n_shell, 3))
+    sites = np.concatenate([shell, bg]).astype(np.float32)
+    density = np.concatenate([np.full(n_shell, 50.0), np.full(n - n_shell, 0.01)]).astype(np.float32)
+    tex = _texels(rng, n, tex_res)
+    off, idx = delaunay_csr(sites) if with_csr else (None, None)
+    return Scene(sites, density, tex, off, idx, name=f"shell{n}")
+
+
+def scene_ellipsoids(n_surface=1_800_000, n_background=200_000, n_ell=20, tex_res=8,
+                     seed=3, with_csr=True):
+    """Config 3: sites clustered on random ellipsoid surfaces plus uniform background.
+
+    Returns (scene, ellipsoids) with ellipsoids = list of (centre, R, semi_axes).
+    """
+    rng = np.random.default_rng(seed)
+    per = n_surface // n_ell
+    pts, ells = [], []
+    for k in range(n_ell):
+        c = rng.uniform(-3.0, 3.0, 3)
+        a = rng.uniform(0.2, 1.0, 3)
+        q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+        q = q * np.sign(np.diag(r))
+        u = rng.normal(size=(per, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        pts.append(c + (u * a) @ q.T + rng.normal(scale=0.01, size=(per, 3)))
+        ells.append((c, q, a))
+    n_surf = per * n_ell
+    bg = rng.uniform(-4.0, 4.0, (n_background, 3))
+    sites = np.concatenate(pts + [bg]).astype(np.float32)
+    density = np.concatenate([np.full(n_surf, 50.0), np.full(n_background, 0.01)]).astype(np.float32)
+    tex = _texels(rng, sites.shape[0], tex_res)
+    off, idx = delaunay_csr(sites) if with_csr else (None, None)
+    return Scene(sites, density, tex, off, idx, name=f"ellipsoids{sites.shape[0]}"), ells, rng
+
+
+def interior_camera(ells, rng, width=1280, height=840, fov_deg=60.0, tmax=14.0,
+                    n_candidates=64) -> Camera:
+    """Config 3 view: seeded interior point with the largest clearance from the
+    ellipsoids (candidates: the origin plus seeded points), looking at the
+    nearest ellipsoid centre."""
+    cands = np.concatenate([np.zeros((1, 3)), rng.uniform(-3.0, 3.0, (n_candidates - 1, 3))])
+    # clearance measured against densely sampled surface points
+    surf = []
+    for c, q, a in ells:
+        u = rng.normal(size=(2000, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        surf.append(c + (u * a) @ q.T)
+    surf = np.concatenate(surf)
+    clear = np.array([np.min(np.linalg.norm(surf - p, axis=1)) for p in cands])
+    pos = cands[int(np.argmax(clear))]
+    centres = np.array([c for c, _, _ in ells])
+    tgt = centres[int(np.argmin(np.linalg.norm(centres - pos, axis=1)))]
+    return Camera(PINHOLE, width, height, look_at(pos, tgt), math.radians(fov_deg), tmax)
+
+
+def config1():
+    """512 uniform sites, 4x4 texels, 64x64 pinhole at (0,0,-3) looking +z."""
+    scene = scene_uniform(512, 4, seed=1)
+    cam = Camera(PINHOLE, 64, 64, look_at((0.0, 0.0, -3.0), (0.0, 0.0, 0.0)),
+                 math.radians(60.0), 6.0)
+    return scene, [cam]
+
+
+def config2(n=100_000, width=800, height=800, n_poses=8, with_csr=True):
+    """100k shell scene, 8x8 texels, 800x800 pinholes on a radius-3 orbit."""
+    scene = scene_shell(n, 8, seed=2, with_csr=with_csr)
+    cams = [Camera(PINHOLE, width, height, orbit_pose(2.0 * math.pi * k / n_poses),
+                   math.radians(60.0), 8.0) for k in range(n_poses)]
+    return scene, cams
+
+
+def config3(scale=1.0, with_csr=True, width=1280, height=840):
+    """2M ellipsoid-surface scene, one 1280x840 pinhole from inside the volume."""
+    scene, ells, rng = scene_ellipsoids(int(1_800_000 * scale), int(200_000 * scale),
+                                        with_csr=with_csr)
+    cam = interior_camera(ells, rng, width, height)
+    return scene, [cam]
+
+
+def config5_cameras(scale=1.0) -> List[Camera]:
+    """Eight mixed views on the radius-3 orbit: 2 pinhole, 2 fisheye 180 deg,
+    2 rolling shutter (0.1 units along camera +x over the frame), 2 thin lens
+    (4 samples per pixel, lens radius 0.05, focus distance 3).
+
+    ``scale`` shrinks the resolutions (1.0 = the full workload)."""
+    def sz(w, h):
+        return max(2, int(round(w * scale))), max(2, int(round(h * scale)))
+    cams = []
+    for k in range(8):
+        pose = orbit_pose(2.0 * math.pi * k / 8)
+        kind = k // 2
+        if kind == 0:
+            w, h = sz(1280, 840)
+            cams.append(Camera(PINHOLE, w, h, pose, math.radians(60.0), 8.0))
+        elif kind == 1:
+            w, h = sz(1024, 1024)
+            cams.append(Camera(FISHEYE, w, h, pose, math.pi, 8.0))
+        elif kind == 2:
+            w, h = sz(960, 540)
+            delta = tuple(float(x) for x in 0.1 * pose[:, 0])
+            cams.append(Camera(ROLLING_SHUTTER, w, h, pose, math.radians(60.0), 8.0,
+                               rs_delta=delta))
+        else:
+            w, h = sz(640, 480)
+            cams.append(Camera(THIN_LENS, w, h, pose, math.radians(60.0), 8.0,
+                               lens_radius=0.05, focus_dist=3.0, spp=4))
+    return cams
+
+
+def config5(n=4_000_000, cam_scale=1.0, with_csr=True):
+    scene = scene_shell(n, 8, seed=5, with_csr=with_csr)
+    return scene, config5_cameras(cam_scale)
+
+
+def upstream(n_rays: int, seed: int, with_gT: bool = True):
+    """Upstream gradients dL/drgb ~ N(0,1) (and dL/dT ~ N(0,1) or zero)."""
+    rng = np.random.default_rng(1000 + seed)
+    g_rgb = rng.normal(size=(n_rays, 3)).astype(np.float32)
+    g_T = rng.normal(size=n_rays).astype(np.float32) if with_gT else np.zeros(n_rays, np.float32)
+    return g_rgb, g_T
+
+
+def crop_pixels(cam: Camera, size: int, seed: int, centre: bool):
+    """Pixel indices (row-major) of a size x size crop: the centre crop or a seeded one."""
+    if centre:
+        x0 = (cam.width - size) // 2
+        y0 = (cam.height - size) // 2
+    else:
+        rng = np.random.default_rng(seed)
+        x0 = int(rng.integers(0, cam.width - size + 1))
+        y0 = int(rng.integers(0, cam.height - size + 1))
+    ys, xs = np.meshgrid(np.arange(y0, y0 + size), np.arange(x0, x0 + size), indexing="ij")
+    return (ys * cam.width + xs).reshape(-1)
+
+
+def sample_pixels(n_total: int, k: int, seed: int):
+    """k distinct pixel/ray indices out of n_total, seeded and sorted."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n_total, size=min(k, n_total), replace=False))
+
+
+def to_f16(tex: np.ndarray) -> np.ndarray:
+    """Round-to-nearest-even cast of f32 texels to IEEE binary16 (input preparation)."""
+    return tex.astype(np.float16)
+
+
+def lattice_sites(n_per_axis: int, spacing: float = 1.0, jitter: float = 0.0, seed: int = 0):
+    """Cubic lattice sites centred on the origin (optionally jittered)."""
+    rng = np.random.default_rng(seed)
+    g = (np.arange(n_per_axis) - (n_per_axis - 1) / 2.0) * spacing
+    pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    if jitter:
+        pts = pts + rng.normal(scale=jitter, size=pts.shape)
+    return pts.astype(np.float32)
+
+
+def scene_from_arrays(sites, density, texels, with_csr=True, name="custom") -> Scene:
+    sites = np.ascontiguousarray(sites, np.float32)
+    off, idx = delaunay_csr(sites) if (with_csr and sites.shape[0] >= 5) else (None, None)
+    return Scene(sites, np.ascontiguousarray(density, np.float32),
+                 np.ascontiguousarray(texels, np.float32), off, idx, name=name)
+
+
+def texels_rgb(n: int, res: int, rgb) -> np.ndarray:
+    tex = np.zeros((n, res, res, 4), np.float32)
+    tex[..., :3] = np.asarray(rgb, np.float32)
+    return tex
