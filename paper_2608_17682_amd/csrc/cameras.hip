@@ -1,0 +1,445 @@
+// Ray generation and the persistent multi-view launch (Sec. 6.5, App. D:
+// several camera models rendered by the same walk; Sec. 5.6: waves take
+// compact screen tiles so neighbouring lanes walk similar cells).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "camera_impl.hpp"
+#include "host_common.hpp"
+#include "locate_impl.hpp"
+#include "voro_device.hpp"
+#include "walk_impl.hpp"
+
+namespace voro {
+
+voro_status launch_locate_brute(const voro_scene* scene, const void* ws, const float* origins,
+                                int U, int32_t* out, hipStream_t st);
+
+// ------------------------------------------------------------- gen_rays
+__global__ void __launch_bounds__(256) k_gen_rays(CamTable ct, float* __restrict__ o,
+                                                  float* __restrict__ d, float* __restrict__ tmax,
+                                                  int n_rays) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rays) return;
+  const int v = find_view(ct.ray_off, ct.V, i);
+  const voro_camera& c = ct.cam[v];
+  const int spp = c.spp;
+  const int local = i - ct.ray_off[v];
+  const int pix = local / spp;
+  const int s = local - pix * spp;
+  const int px = pix % c.width;
+  const int py = pix / c.width;
+  float ox, oy, oz, dx, dy, dz, tm;
+  gen_ray(c, ct.g[v], px, py, s, ox, oy, oz, dx, dy, dz, tm);
+  o[3 * (size_t)i] = ox;
+  o[3 * (size_t)i + 1] = oy;
+  o[3 * (size_t)i + 2] = oz;
+  d[3 * (size_t)i] = dx;
+  d[3 * (size_t)i + 1] = dy;
+  d[3 * (size_t)i + 2] = dz;
+  tmax[i] = tm;
+}
+
+// ---------------------------------------------------- persistent launch
+//
+// Work unit: one wave-sized screen tile (tile_w x tile_h rays) of one view.
+// A thin-lens view's samples form a (W g) x (H g) ray grid so a tile holds
+// neighbouring samples.  Workgroup b runs on XCD b % 8; each XCD first
+// drains its own contiguous eighth of the tile sequence (its L2 sees one
+// image region), then helps the other XCDs.  Counters live in the workspace
+// and are zeroed by k_views_setup before every launch.
+constexpr int kXcd = 8;
+
+struct ViewsArgs {
+  DevScene s;
+  WalkParams w;
+  CamTable ct;
+  const int32_t* center_cell;  // [V] cell of each camera centre
+  unsigned int* counters;      // [kXcd]
+  int total_tiles;
+  int tile_w, tile_h;
+  // forward
+  float* rgb;
+  float* T;
+  float* ray_rgbT;
+  int32_t* nsteps;
+  // backward
+  const float* rgb_in;
+  const float* T_in;
+  const float* ray_rgbT_in;
+  const float* g_rgb;
+  const float* g_T;
+  Grads g;
+  unsigned long long* stats;
+};
+
+struct Centers {
+  float c[3 * VORO_MAX_VIEWS];
+};
+
+// camera centres into the workspace (they travel as kernel arguments, so no
+// host-to-device copy is needed) and the tile counters zeroed
+__global__ void k_views_setup(Centers c, float* dst, int n, unsigned int* ctr) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = c.c[i];
+  if (i < kXcd) ctr[i] = 0u;
+}
+
+// next tile for this wave, or -1 when every XCD's range is drained
+__device__ __forceinline__ int next_tile(unsigned int* counters, int total, int xcd, int lane,
+                                         int& probe) {
+  while (probe < kXcd) {
+    const int x = (xcd + probe) % kXcd;
+    const int lo = (int)(((long)total * x) / kXcd);
+    const int hi = (int)(((long)total * (x + 1)) / kXcd);
+    int t = 0;
+    if (lane == 0) t = (int)atomicAdd(&counters[x], 1u);
+    t = __shfl(t, 0);
+    if (lo + t < hi) return lo + t;
+    ++probe;
+  }
+  return -1;
+}
+
+struct TileRay {
+  int view, px, py, s, ray, pixel;
+};
+
+// decode (tile, lane group) into a ray; returns false outside the view
+__device__ __forceinline__ bool tile_ray(const CamTable& ct, int tile, int grp, int tile_w,
+                                         int tile_h, TileRay& tr) {
+  const int v = find_view(ct.tile_off, ct.V, tile);
+  const voro_camera& c = ct.cam[v];
+  const int g = ct.g[v];
+  const int gw = c.width * g;
+  const int gh = c.height * g;
+  const int tiles_x = (gw + tile_w - 1) / tile_w;
+  const int local = tile - ct.tile_off[v];
+  const int X = (local % tiles_x) * tile_w + grp % tile_w;
+  const int Y = (local / tiles_x) * tile_h + grp / tile_w;
+  if (X >= gw || Y >= gh) return false;
+  tr.view = v;
+  tr.px = X / g;
+  tr.py = Y / g;
+  tr.s = (X % g) + g * (Y % g);
+  tr.pixel = tr.py * c.width + tr.px;
+  tr.ray = ct.ray_off[v] + tr.pixel * c.spp + tr.s;
+  return true;
+}
+
+__device__ __forceinline__ RayIn views_ray(const ViewsArgs& a, const TileRay& tr, bool* capped) {
+  const voro_camera& c = a.ct.cam[tr.view];
+  RayIn r;
+  gen_ray(c, a.ct.g[tr.view], tr.px, tr.py, tr.s, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, r.tmax);
+  r.start = a.center_cell[tr.view];
+  const bool moved = c.model == VORO_CAM_ROLLING_SHUTTER ||
+                     (c.model == VORO_CAM_THIN_LENS && c.lens_radius > 0.0f);
+  if (moved && r.tmax > 0.0f && r.start >= 0 && r.start < a.s.n)
+    r.start = nearest_walk(a.s, r.ox, r.oy, r.oz, r.start, capped);
+  return r;
+}
+
+template <int LPR, int TEX>
+__global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / LPR;
+  const int sub = lane % LPR;
+  const int xcd = blockIdx.x % kXcd;
+  Counters cnt;
+  uint32_t capped_n = 0;
+  int probe = 0;
+  for (;;) {
+    const int tile = next_tile(a.counters, a.total_tiles, xcd, lane, probe);
+    if (tile < 0) break;
+    TileRay tr;
+    if (tile_ray(a.ct, tile, grp, a.tile_w, a.tile_h, tr)) {
+      bool capped = false;
+      const RayIn r = views_ray(a, tr, &capped);
+      capped_n += capped ? 1u : 0u;
+      const RayOut out = walk_forward<LPR, TEX>(a.s, a.w, r, sub, nullptr, 0, cnt);
+      if (sub == 0) {
+        const voro_camera& c = a.ct.cam[tr.view];
+        if (c.spp == 1) {
+          const size_t p = (size_t)a.ct.pix_off[tr.view] + tr.pixel;
+          a.rgb[3 * p] = out.r;
+          a.rgb[3 * p + 1] = out.g;
+          a.rgb[3 * p + 2] = out.b;
+          a.T[p] = out.T;
+        }
+        if (a.ray_rgbT) {
+          reinterpret_cast<float4*>(a.ray_rgbT)[tr.ray] = make_float4(out.r, out.g, out.b, out.T);
+        }
+        if (a.nsteps) a.nsteps[tr.ray] = out.k;
+      }
+    }
+  }
+  if (a.stats) {
+    flush_counters(cnt, sub == 0, lane, a.stats);
+    const uint32_t cp = wave_sum_u32(sub == 0 ? capped_n : 0u);
+    if (lane == 0 && cp) atomicAdd(&a.stats[VORO_STAT_LOCATE_CAP], (unsigned long long)cp);
+  }
+}
+
+template <int LPR, int TEX>
+__global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / LPR;
+  const int sub = lane % LPR;
+  const int xcd = blockIdx.x % kXcd;
+  Counters cnt;
+  int probe = 0;
+  for (;;) {
+    const int tile = next_tile(a.counters, a.total_tiles, xcd, lane, probe);
+    if (tile < 0) break;
+    TileRay tr;
+    if (tile_ray(a.ct, tile, grp, a.tile_w, a.tile_h, tr)) {
+      bool capped = false;
+      const RayIn r = views_ray(a, tr, &capped);
+      const voro_camera& c = a.ct.cam[tr.view];
+      const size_t p = (size_t)a.ct.pix_off[tr.view] + tr.pixel;
+      Upstream u;
+      const float share = 1.0f / (float)c.spp;
+      if (c.spp == 1) {
+        u.Cr = a.rgb_in[3 * p];
+        u.Cg = a.rgb_in[3 * p + 1];
+        u.Cb = a.rgb_in[3 * p + 2];
+        u.Tf = a.T_in[p];
+      } else {
+        const float4 q = reinterpret_cast<const float4*>(a.ray_rgbT_in)[tr.ray];
+        u.Cr = q.x;
+        u.Cg = q.y;
+        u.Cb = q.z;
+        u.Tf = q.w;
+      }
+      u.gr = a.g_rgb[3 * p] * share;
+      u.gg = a.g_rgb[3 * p + 1] * share;
+      u.gb = a.g_rgb[3 * p + 2] * share;
+      u.gT = a.g_T ? a.g_T[p] * share : 0.0f;
+      walk_backward<LPR, TEX>(a.s, a.w, r, u, sub, a.g, cnt);
+    }
+  }
+  if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
+}
+
+// pixel = mean of its samples, in sample order
+__global__ void __launch_bounds__(256) k_views_resolve(CamTable ct, const float4* __restrict__ ray_rgbT,
+                                                       float* __restrict__ rgb, float* __restrict__ T,
+                                                       int n_pixels) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pixels) return;
+  const int v = find_view(ct.pix_off, ct.V, p);
+  const int spp = ct.cam[v].spp;
+  if (spp == 1) return;
+  const int base = ct.ray_off[v] + (p - ct.pix_off[v]) * spp;
+  float r = 0.0f, g = 0.0f, b = 0.0f, t = 0.0f;
+  for (int s = 0; s < spp; ++s) {
+    const float4 q = ray_rgbT[base + s];
+    r += q.x;
+    g += q.y;
+    b += q.z;
+    t += q.w;
+  }
+  const float inv = 1.0f / (float)spp;
+  rgb[3 * (size_t)p] = r * inv;
+  rgb[3 * (size_t)p + 1] = g * inv;
+  rgb[3 * (size_t)p + 2] = b * inv;
+  T[p] = t * inv;
+}
+
+static CamTable make_table(const voro_camera* cams, int V, int tile_w, int tile_h) {
+  CamTable ct;
+  std::memset(&ct, 0, sizeof(ct));
+  ct.V = V;
+  int ro = 0, po = 0, to = 0;
+  for (int v = 0; v < V; ++v) {
+    ct.cam[v] = cams[v];
+    const int g = (int)std::lround(std::sqrt((double)cams[v].spp));
+    ct.g[v] = g;
+    ct.ray_off[v] = ro;
+    ct.pix_off[v] = po;
+    ct.tile_off[v] = to;
+    ro += cams[v].width * cams[v].height * cams[v].spp;
+    po += cams[v].width * cams[v].height;
+    if (tile_w > 0) {
+      const int gw = cams[v].width * g, gh = cams[v].height * g;
+      to += ((gw + tile_w - 1) / tile_w) * ((gh + tile_h - 1) / tile_h);
+    }
+  }
+  for (int v = V; v <= VORO_MAX_VIEWS; ++v) {
+    ct.ray_off[v] = ro;
+    ct.pix_off[v] = po;
+    ct.tile_off[v] = to;
+  }
+  return ct;
+}
+
+template <int LPR, int TEX>
+static int persistent_blocks(bool backward, int block) {
+  static int cached[2][5] = {};
+  int& c = cached[backward ? 1 : 0][block / 128];
+  if (c) return c;
+  int dev = 0, cus = 0, occ = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (backward)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX>, block, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX>, block, 0);
+  (void)hipGetLastError();
+  c = max(kXcd, max(1, cus) * max(1, occ));
+  c = (c / kXcd) * kXcd;
+  return c;
+}
+
+template <int LPR, int TEX>
+static void launch_views_t(bool backward, const ViewsArgs& a, int block, hipStream_t st) {
+  const int blocks = persistent_blocks<LPR, TEX>(backward, block);
+  if (backward)
+    hipLaunchKernelGGL((k_views_bwd<LPR, TEX>), dim3(blocks), dim3(block), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_views_fwd<LPR, TEX>), dim3(blocks), dim3(block), 0, st, a);
+}
+
+template <int TEX>
+static void launch_views_lpr(int lpr, bool backward, const ViewsArgs& a, int block,
+                             hipStream_t st) {
+  switch (lpr) {
+    case 1: launch_views_t<1, TEX>(backward, a, block, st); break;
+    case 2: launch_views_t<2, TEX>(backward, a, block, st); break;
+    case 4: launch_views_t<4, TEX>(backward, a, block, st); break;
+    case 8: launch_views_t<8, TEX>(backward, a, block, st); break;
+    default: launch_views_t<16, TEX>(backward, a, block, st); break;
+  }
+}
+
+static voro_status views_common(bool backward, const voro_scene* scene, void* ws, size_t ws_bytes,
+                                const voro_camera* cams, int32_t V, const voro_params* params,
+                                ViewsArgs& a, int64_t* n_rays, int64_t* n_pixels, bool* any_spp,
+                                void* stream) {
+  voro_status st;
+  if ((st = check_scene(scene)) != VORO_OK) return st;
+  if ((st = check_ws(scene, ws, ws_bytes)) != VORO_OK) return st;
+  if ((st = check_params(params, backward)) != VORO_OK) return st;
+  if ((st = check_cameras(cams, V, n_rays, n_pixels)) != VORO_OK) return st;
+  bool spp = false;
+  for (int v = 0; v < V; ++v) spp = spp || cams[v].spp > 1;
+  *any_spp = spp;
+  if ((st = check_device()) != VORO_OK) return st;
+  const Launch L = resolve_launch(params);
+  const WsLayout W = ws_layout(scene->n_sites, scene->n_edges);
+  char* base = (char*)ws + W.counters;
+  a.counters = reinterpret_cast<unsigned int*>(base);
+  int32_t* centers = reinterpret_cast<int32_t*>(base + 256);
+  float* origins = reinterpret_cast<float*>(base + 512);
+  a.center_cell = centers;
+  a.s = dev_scene(scene, ws);
+  a.w = walk_params(params);
+  a.ct = make_table(cams, V, L.tile_w, L.tile_h);
+  a.total_tiles = a.ct.tile_off[V];
+  a.tile_w = L.tile_w;
+  a.tile_h = L.tile_h;
+  const hipStream_t s = (hipStream_t)stream;
+  // camera centres -> device (through kernel arguments), then their cells
+  Centers cc;
+  for (int v = 0; v < V; ++v) {
+    cc.c[3 * v] = cams[v].c2w[3];
+    cc.c[3 * v + 1] = cams[v].c2w[7];
+    cc.c[3 * v + 2] = cams[v].c2w[11];
+  }
+  hipLaunchKernelGGL(k_views_setup, dim3(1), dim3(64), 0, s, cc, origins, 3 * V, a.counters);
+  if ((st = check_launch("views: setup")) != VORO_OK) return st;
+  if ((st = launch_locate_brute(scene, ws, origins, V, centers, s)) != VORO_OK) return st;
+  const int block = L.block;
+  switch (scene->tex_dtype) {
+    case VORO_TEX_F32: launch_views_lpr<VORO_TEX_F32>(L.lpr, backward, a, block, s); break;
+    case VORO_TEX_F16: launch_views_lpr<VORO_TEX_F16>(L.lpr, backward, a, block, s); break;
+    default: launch_views_lpr<VORO_TEX_BF16>(L.lpr, backward, a, block, s); break;
+  }
+  return check_launch(backward ? "voro_render_views_bwd" : "voro_render_views_fwd");
+}
+
+}  // namespace voro
+
+using namespace voro;
+
+extern "C" {
+
+voro_status voro_gen_rays(const voro_camera* cams, int32_t V, float* o, float* d, float* tmax,
+                          void* stream) {
+  int64_t nr = 0, np = 0;
+  voro_status st = check_cameras(cams, V, &nr, &np);
+  if (st != VORO_OK) return st;
+  if (!o || !d || !tmax) return fail(VORO_EINVAL, "ray outputs must not be NULL");
+  if ((st = check_device()) != VORO_OK) return st;
+  const CamTable ct = make_table(cams, V, 0, 0);
+  const int n = (int)nr;
+  hipLaunchKernelGGL(k_gen_rays, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, ct, o,
+                     d, tmax, n);
+  return check_launch("voro_gen_rays");
+}
+
+voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_bytes,
+                                  const voro_camera* cams, int32_t V, const voro_params* params,
+                                  float* rgb, float* T, float* ray_rgbT, int32_t* nsteps,
+                                  uint64_t* stats, void* stream) {
+  if (!rgb || !T) return fail(VORO_EINVAL, "rgb and T must not be NULL");
+  if (ray_rgbT && !aligned(ray_rgbT, 16)) return fail(VORO_EINVAL, "ray_rgbT must be 16-byte aligned");
+  ViewsArgs a = {};
+  a.rgb = rgb;
+  a.T = T;
+  a.ray_rgbT = ray_rgbT;
+  a.nsteps = nsteps;
+  a.stats = reinterpret_cast<unsigned long long*>(stats);
+  int64_t nr = 0, np = 0;
+  bool any_spp = false;
+  // validate everything (including ray_rgbT's presence) before enqueueing
+  voro_status st = check_cameras(cams, V, &nr, &np);
+  if (st != VORO_OK) return st;
+  for (int v = 0; v < V; ++v)
+    if (cams[v].spp > 1 && !ray_rgbT)
+      return fail(VORO_EINVAL, "ray_rgbT is required when a view has spp > 1");
+  st = views_common(false, scene, ws, ws_bytes, cams, V, params, a, &nr, &np, &any_spp, stream);
+  if (st != VORO_OK) return st;
+  if (any_spp) {
+    const int n = (int)np;
+    hipLaunchKernelGGL(k_views_resolve, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       a.ct, reinterpret_cast<const float4*>(ray_rgbT), rgb, T, n);
+    st = check_launch("voro_render_views_fwd: resolve");
+  }
+  return st;
+}
+
+voro_status voro_render_views_bwd(const voro_scene* scene, void* ws, size_t ws_bytes,
+                                  const voro_camera* cams, int32_t V, const voro_params* params,
+                                  const float* rgb, const float* T, const float* ray_rgbT,
+                                  const float* g_rgb, const float* g_T, float* g_sites,
+                                  float* g_density, float* g_texels, uint64_t* stats,
+                                  void* stream) {
+  if (!rgb || !T || !g_rgb) return fail(VORO_EINVAL, "rgb, T and g_rgb must not be NULL");
+  if (!g_sites || !g_density || !g_texels)
+    return fail(VORO_EINVAL, "gradient outputs must not be NULL");
+  if (ray_rgbT && !aligned(ray_rgbT, 16)) return fail(VORO_EINVAL, "ray_rgbT must be 16-byte aligned");
+  if (!aligned(g_texels, 16)) return fail(VORO_EINVAL, "g_texels must be 16-byte aligned");
+  int64_t nr = 0, np = 0;
+  voro_status st = check_cameras(cams, V, &nr, &np);
+  if (st != VORO_OK) return st;
+  for (int v = 0; v < V; ++v)
+    if (cams[v].spp > 1 && !ray_rgbT)
+      return fail(VORO_EINVAL, "ray_rgbT is required when a view has spp > 1");
+  ViewsArgs a = {};
+  a.rgb_in = rgb;
+  a.T_in = T;
+  a.ray_rgbT_in = ray_rgbT;
+  a.g_rgb = g_rgb;
+  a.g_T = g_T;
+  a.g.sites = g_sites;
+  a.g.density = g_density;
+  a.g.texels = g_texels;
+  a.stats = reinterpret_cast<unsigned long long*>(stats);
+  bool any_spp = false;
+  return views_common(true, scene, ws, ws_bytes, cams, V, params, a, &nr, &np, &any_spp, stream);
+}
+
+}  // extern "C"

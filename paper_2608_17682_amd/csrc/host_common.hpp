@@ -1,0 +1,57 @@
+// Host-side helpers shared by the C entry points: error reporting, argument
+// validation, workspace layout and launch checks.  No device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+
+#include "voro.h"
+
+namespace voro {
+
+// thread-local last-error text (defined in api.cpp)
+void set_error(const char* fmt, ...);
+void clear_error();
+
+voro_status fail(voro_status st, const char* fmt, ...);
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace layout: cell records, edge records, nearest-site partials,
+// persistent-launch counters and per-view start cells.
+constexpr int kLocateBruteMax = 64;    // origins searched by brute force
+constexpr int kLocateChunks = 256;     // max partial results per origin
+struct WsLayout {
+  size_t cells, edges, locate, counters, total;
+};
+
+inline WsLayout ws_layout(int32_t n, int64_t m) {
+  WsLayout L;
+  L.cells = 0;
+  L.edges = align256((size_t)n * 32);
+  L.locate = align256(L.edges + (size_t)m * 16);
+  L.counters = align256(L.locate + (size_t)kLocateBruteMax * kLocateChunks * 16);
+  L.total = align256(L.counters + 4096);
+  return L;
+}
+
+voro_status check_scene(const voro_scene* s);
+voro_status check_ws(const voro_scene* s, const void* ws, size_t ws_bytes);
+voro_status check_params(const voro_params* p, bool backward);
+voro_status check_cameras(const voro_camera* cams, int32_t V, int64_t* n_rays, int64_t* n_pixels);
+voro_status check_device();
+voro_status check_launch(const char* what);
+
+inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+// effective launch parameters after defaults
+struct Launch {
+  int lpr, tile_w, tile_h, block;
+};
+Launch resolve_launch(const voro_params* p);
+
+}  // namespace voro

@@ -1,0 +1,362 @@
+// Device-side building blocks of the Voronoi walk, shared by every kernel so
+// that all launches (explicit rays, persistent multi-view, forward and
+// adjoint) take bit-identical decisions for the same ray.
+//
+// Compiled with -ffp-contract=off: every fused multiply-add below is written
+// out with fmaf, so no launch context can change the rounding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "voro.h"
+
+namespace voro {
+
+constexpr float kInf = __builtin_huge_valf();
+
+// ----------------------------------------------------------- packed scene
+//
+// Cell record, 32 bytes = two float4: {x, y, z, sigma}, {edge_off, deg, 0, 0}
+// (the ints stored by bit pattern).  Edge record, 16 bytes: {n.x, n.y, n.z, j}
+// with n = p_j - p_i in FP32 and j the neighbour id (bit pattern).  A cell's
+// edges are contiguous, so one exit search reads deg consecutive float4s.
+struct DevScene {
+  const float4* __restrict__ cells;
+  const float4* __restrict__ edges;
+  const void* __restrict__ texels;
+  int n;
+  int res;
+};
+
+struct Cell {
+  float px, py, pz, sigma;
+  int off, deg;
+};
+
+__device__ __forceinline__ Cell load_cell(const float4* __restrict__ cells, int i) {
+  const float4 a = cells[2 * (size_t)i];
+  const float4 b = cells[2 * (size_t)i + 1];
+  Cell c;
+  c.px = a.x;
+  c.py = a.y;
+  c.pz = a.z;
+  c.sigma = a.w;
+  c.off = __float_as_int(b.x);
+  c.deg = __float_as_int(b.y);
+  return c;
+}
+
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+  return fmaf(az, bz, fmaf(ay, by, ax * bx));
+}
+
+// ----------------------------------------------------- exit-face search
+//
+// Among the Delaunay neighbours j of the current cell i, the ray leaves
+// through the bisector it reaches first moving forward (Sec. 3.1).  With
+// x_in = o + t_in w the entry point and q = x_in - p_i, the bisector of
+// (p_i, p_j) is crossed at t_in + (|n|^2/2 - n.q) / (n.w), n = p_j - p_i,
+// and only faces with n.w > 0 lie ahead.  Measuring from x_in keeps the
+// numerator small (cell-sized), and an error in t_in cancels: the result
+// is the plane's own crossing parameter.
+//
+// The search keeps the best two candidates (t, j) in lexicographic order
+// (exact ties go to the smaller id), so the result does not depend on the
+// order or the lane split of the neighbour list.
+struct Top2 {
+  float t1;
+  int j1;
+  float t2;
+  int j2;
+};
+
+__device__ __forceinline__ bool lex_less(float ta, int ja, float tb, int jb) {
+  return (ta < tb) || (ta == tb && (unsigned)ja < (unsigned)jb);
+}
+
+__device__ __forceinline__ void top2_insert(Top2& r, float t, int j) {
+  if (lex_less(t, j, r.t1, r.j1)) {
+    r.t2 = r.t1;
+    r.j2 = r.j1;
+    r.t1 = t;
+    r.j1 = j;
+  } else if (lex_less(t, j, r.t2, r.j2)) {
+    r.t2 = t;
+    r.j2 = j;
+  }
+}
+
+// merge another lane's top two into r (both are sorted pairs)
+__device__ __forceinline__ void top2_merge(Top2& r, float u1, int k1, float u2, int k2) {
+  if (lex_less(u1, k1, r.t1, r.j1)) {
+    // other's best wins; second is min(r.first, other's second)
+    float s = r.t1;
+    int sj = r.j1;
+    if (lex_less(u2, k2, s, sj)) {
+      s = u2;
+      sj = k2;
+    }
+    r.t1 = u1;
+    r.j1 = k1;
+    r.t2 = s;
+    r.j2 = sj;
+  } else if (lex_less(u1, k1, r.t2, r.j2)) {
+    r.t2 = u1;
+    r.j2 = k1;
+  }
+}
+
+template <int LPR>
+__device__ __forceinline__ Top2 exit_search(const float4* __restrict__ edges, int off, int deg,
+                                            int sub, float qx, float qy, float qz, float dx,
+                                            float dy, float dz) {
+  Top2 r;
+  r.t1 = kInf;
+  r.j1 = -1;
+  r.t2 = kInf;
+  r.j2 = -1;
+  const float4* e = edges + off;
+#pragma unroll 4
+  for (int k = sub; k < deg; k += LPR) {
+    const float4 E = e[k];
+    const float b = dot3(E.x, E.y, E.z, dx, dy, dz);
+    if (b > 0.0f) {
+      const float h = 0.5f * dot3(E.x, E.y, E.z, E.x, E.y, E.z);
+      const float nq = dot3(E.x, E.y, E.z, qx, qy, qz);
+      const float t = (h - nq) * __builtin_amdgcn_rcpf(b);
+      top2_insert(r, t, __float_as_int(E.w));
+    }
+  }
+  if constexpr (LPR > 1) {
+#pragma unroll
+    for (int m = 1; m < LPR; m <<= 1) {
+      const float u1 = __shfl_xor(r.t1, m);
+      const int k1 = __shfl_xor(r.j1, m);
+      const float u2 = __shfl_xor(r.t2, m);
+      const int k2 = __shfl_xor(r.j2, m);
+      top2_merge(r, u1, k1, u2, k2);
+    }
+  }
+  return r;
+}
+
+// Crossing parameter of the bisector of (p_i, p_j) in FP64 from the FP32
+// inputs: t = n.(m - o) / (n.w), n = p_j - p_i, m = (p_i + p_j)/2; +inf
+// when the face does not lie ahead.
+__device__ __forceinline__ double cross64(const float4* __restrict__ cells, int i, int j, double ox,
+                                          double oy, double oz, double dx, double dy, double dz) {
+  const float4 a = cells[2 * (size_t)i];
+  const float4 c = cells[2 * (size_t)j];
+  const double nx = (double)c.x - (double)a.x;
+  const double ny = (double)c.y - (double)a.y;
+  const double nz = (double)c.z - (double)a.z;
+  const double b = __dadd_rn(__dadd_rn(__dmul_rn(nx, dx), __dmul_rn(ny, dy)), __dmul_rn(nz, dz));
+  if (!(b > 0.0)) return __builtin_huge_val();
+  const double mx = 0.5 * ((double)a.x + (double)c.x);
+  const double my = 0.5 * ((double)a.y + (double)c.y);
+  const double mz = 0.5 * ((double)a.z + (double)c.z);
+  const double num = __dadd_rn(__dadd_rn(__dmul_rn(nx, mx - ox), __dmul_rn(ny, my - oy)),
+                               __dmul_rn(nz, mz - oz));
+  return num / b;
+}
+
+// The exit of cell i: absolute exit parameter and the next cell (-1: none).
+// Near ties of the FP32 search are re-decided in FP64.
+struct Exit {
+  float t;
+  int next;
+  bool redecided;
+};
+
+__device__ __forceinline__ Exit decide_exit(const Top2& r, const float4* __restrict__ cells, int i,
+                                            float t_in, float tie_window, float ox, float oy,
+                                            float oz, float dx, float dy, float dz) {
+  Exit x;
+  x.redecided = false;
+  if (r.j1 < 0) {
+    x.t = kInf;
+    x.next = -1;
+    return x;
+  }
+  x.t = t_in + r.t1;
+  x.next = r.j1;
+  if (r.j2 >= 0 && (r.t2 - r.t1) <= tie_window * fmaxf(1.0f, fabsf(x.t))) {
+    const double t1 = cross64(cells, i, r.j1, ox, oy, oz, dx, dy, dz);
+    const double t2 = cross64(cells, i, r.j2, ox, oy, oz, dx, dy, dz);
+    double tb = t1;
+    int jb = r.j1;
+    if (t2 < t1 || (t2 == t1 && r.j2 < r.j1)) {
+      tb = t2;
+      jb = r.j2;
+    }
+    if (tb < __builtin_huge_val()) {
+      x.t = (float)tb;
+      x.next = jb;
+    }
+    x.redecided = true;
+  }
+  return x;
+}
+
+// ------------------------------------------------------ octahedral taps
+//
+// Sec. 5.1: q = d / |d|_1; upper hemisphere (d_z >= 0) -> (q_x, q_y), lower
+// -> ((1-|q_y|) sgn q_x, (1-|q_x|) sgn q_y) with sgn(0) = +1.  Texel space
+// is corner-aligned: x = (u+1)/2 (R-1), column c0 = min(floor x, R-2),
+// fraction x - c0 (rows likewise from v).  The four taps are
+// (r0,c0), (r0,c0+1), (r0+1,c0), (r0+1,c0+1).
+struct Taps {
+  int base;  // r0 * R + c0
+  float w00, w01, w10, w11;
+};
+
+__device__ __forceinline__ float sgn_nz(float x) { return x >= 0.0f ? 1.0f : -1.0f; }
+
+__device__ __forceinline__ Taps make_taps(float dx, float dy, float dz, int R) {
+  const float s = fabsf(dx) + fabsf(dy) + fabsf(dz);
+  const float qx = dx / s;
+  const float qy = dy / s;
+  float u, v;
+  if (dz >= 0.0f) {
+    u = qx;
+    v = qy;
+  } else {
+    u = (1.0f - fabsf(qy)) * sgn_nz(qx);
+    v = (1.0f - fabsf(qx)) * sgn_nz(qy);
+  }
+  const float x = (u + 1.0f) * 0.5f * (float)(R - 1);
+  const float y = (v + 1.0f) * 0.5f * (float)(R - 1);
+  int c0 = (int)floorf(x);
+  int r0 = (int)floorf(y);
+  c0 = max(0, min(c0, R - 2));
+  r0 = max(0, min(r0, R - 2));
+  const float fx = x - (float)c0;
+  const float fy = y - (float)r0;
+  Taps t;
+  t.base = r0 * R + c0;
+  t.w00 = (1.0f - fx) * (1.0f - fy);
+  t.w01 = fx * (1.0f - fy);
+  t.w10 = (1.0f - fx) * fy;
+  t.w11 = fx * fy;
+  return t;
+}
+
+// texel storage
+template <int TEX>
+struct TexelT;
+
+template <>
+struct TexelT<VORO_TEX_F32> {
+  __device__ __forceinline__ static float4 load(const void* __restrict__ p, size_t idx) {
+    return reinterpret_cast<const float4*>(p)[idx];
+  }
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+template <>
+struct TexelT<VORO_TEX_BF16> {
+  __device__ __forceinline__ static float4 load(const void* __restrict__ p, size_t idx) {
+    const uint2 v = reinterpret_cast<const uint2*>(p)[idx];
+    return make_float4(bf16_to_f32(v.x & 0xffffu), bf16_to_f32(v.x >> 16),
+                       bf16_to_f32(v.y & 0xffffu), bf16_to_f32(v.y >> 16));
+  }
+};
+
+template <>
+struct TexelT<VORO_TEX_F16> {
+  __device__ __forceinline__ static float4 load(const void* __restrict__ p, size_t idx) {
+    const uint2 v = reinterpret_cast<const uint2*>(p)[idx];
+    const _Float16 a = __builtin_bit_cast(_Float16, (uint16_t)(v.x & 0xffffu));
+    const _Float16 b = __builtin_bit_cast(_Float16, (uint16_t)(v.x >> 16));
+    const _Float16 c = __builtin_bit_cast(_Float16, (uint16_t)(v.y & 0xffffu));
+    const _Float16 d = __builtin_bit_cast(_Float16, (uint16_t)(v.y >> 16));
+    return make_float4((float)a, (float)b, (float)c, (float)d);
+  }
+};
+
+// Bilinear colour of cell i at the ray's taps.
+template <int TEX>
+__device__ __forceinline__ void texel_rgb(const void* __restrict__ tex, int i, int R, const Taps& tp,
+                                          float& r, float& g, float& b) {
+  const size_t base = (size_t)i * (size_t)(R * R) + (size_t)tp.base;
+  const float4 a = TexelT<TEX>::load(tex, base);
+  const float4 c = TexelT<TEX>::load(tex, base + 1);
+  const float4 e = TexelT<TEX>::load(tex, base + R);
+  const float4 f = TexelT<TEX>::load(tex, base + R + 1);
+  r = fmaf(tp.w11, f.x, fmaf(tp.w10, e.x, fmaf(tp.w01, c.x, tp.w00 * a.x)));
+  g = fmaf(tp.w11, f.y, fmaf(tp.w10, e.y, fmaf(tp.w01, c.y, tp.w00 * a.y)));
+  b = fmaf(tp.w11, f.z, fmaf(tp.w10, e.z, fmaf(tp.w01, c.z, tp.w00 * a.z)));
+}
+
+// ---------------------------------------------------------- segment math
+//
+// Sec. 3.2: delta = max(min(exit, tmax) - t_in, 0), alpha = 1 - exp(-sigma
+// delta), w = T alpha, T <- T exp(-sigma delta).
+struct Segment {
+  float delta;
+  float trans;  // exp(-sigma delta)
+  float alpha;
+};
+
+__device__ __forceinline__ Segment segment(float exit_t, float tmax, float t_in, float sigma) {
+  Segment s;
+  const float t_out = fminf(exit_t, tmax);
+  s.delta = fmaxf(t_out - t_in, 0.0f);
+  s.trans = expf(-(sigma * s.delta));
+  s.alpha = 1.0f - s.trans;
+  return s;
+}
+
+// ------------------------------------------------------- launch geometry
+//
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Renumber them so that each XCD walks one contiguous range of
+// screen tiles and its L2 sees spatially coherent cells.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  constexpr int X = 8;
+  const int q = nblocks / X;
+  const int r = nblocks % X;
+  const int x = b % X;
+  const int k = b / X;
+  return x * q + min(x, r) + k;
+}
+
+// Map (logical block, wave, lane group) to a ray index, or -1.
+struct RayMap {
+  int n_rays;
+  int img_w;   // 0: linear order
+  int img_h;
+  int tile_w;
+  int tile_h;
+  int blocks_x;  // image blocks per row (tiled mode)
+};
+
+template <int LPR>
+__device__ __forceinline__ int map_ray(const RayMap& m, int lblock, int wave, int nwaves, int grp) {
+  constexpr int RPW = 64 / LPR;  // rays per wave
+  if (m.img_w <= 0) {
+    const long r = ((long)lblock * nwaves + wave) * RPW + grp;
+    return r < m.n_rays ? (int)r : -1;
+  }
+  // waves of a block form a wx x wy grid of tiles
+  const int wx = nwaves >= 2 ? 2 : 1;
+  const int bw = m.tile_w * wx;
+  const int bh = m.tile_h * (nwaves / wx);
+  const int bx = lblock % m.blocks_x;
+  const int by = lblock / m.blocks_x;
+  const int x = bx * bw + (wave % wx) * m.tile_w + grp % m.tile_w;
+  const int y = by * bh + (wave / wx) * m.tile_h + grp / m.tile_w;
+  if (x >= m.img_w || y >= m.img_h) return -1;
+  return y * m.img_w + x;
+}
+
+// wave-wide sum of a 32-bit counter
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+}  // namespace voro

@@ -1,0 +1,326 @@
+// Scene packing, forward walk and its adjoint (explicit rays).
+//
+// Sec. 3.1: from the cell holding the origin, repeatedly cross the nearest
+// forward bisector between the current site and its Delaunay neighbours.
+// Sec. 3.2: per visited cell alpha = 1 - exp(-sigma delta), front-to-back
+// compositing C = sum T_k alpha_k c_k, stop once T falls below t_stop.
+// Sec. 5.1: c_k is the cell's octahedral texture sampled bilinearly at the
+// ray direction.  Sec. 5.6: the low-weight texel lookup may be skipped.
+#include <hip/hip_runtime.h>
+
+#include "host_common.hpp"
+#include "voro_device.hpp"
+#include "walk_impl.hpp"
+
+namespace voro {
+
+// ------------------------------------------------------------------ prepare
+// 16 lanes per cell: lane 0 writes the cell record, all 16 stride over the
+// cell's adjacency row writing edge records (coalesced 256-byte runs).
+struct PrepArgs {
+  const float* sites;
+  const float* density;
+  const int32_t* nbr_off;
+  const int32_t* nbr_idx;
+  int n;
+  int m;
+  float4* cells;
+  float4* edges;
+  unsigned long long* stats;
+};
+
+__global__ void __launch_bounds__(256) k_prepare(PrepArgs a) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long cell = gid >> 4;
+  const int l16 = threadIdx.x & 15;
+  if (cell >= a.n) return;
+  const int i = (int)cell;
+  const int off = a.nbr_off[i];
+  const int end = a.nbr_off[i + 1];
+  const bool bad_row = off < 0 || end < off || end > a.m;
+  const float px = a.sites[3 * (size_t)i];
+  const float py = a.sites[3 * (size_t)i + 1];
+  const float pz = a.sites[3 * (size_t)i + 2];
+  if (l16 == 0) {
+    a.cells[2 * (size_t)i] = make_float4(px, py, pz, a.density[i]);
+    a.cells[2 * (size_t)i + 1] =
+        make_float4(__int_as_float(bad_row ? 0 : off), __int_as_float(bad_row ? 0 : end - off),
+                    0.0f, 0.0f);
+    if (bad_row && a.stats) atomicAdd(&a.stats[VORO_STAT_BAD_CSR], 1ull);
+  }
+  if (bad_row) return;
+  for (int e = off + l16; e < end; e += 16) {
+    const int j = a.nbr_idx[e];
+    float4 E;
+    if (j < 0 || j >= a.n || j == i) {
+      // never followed: n = 0 gives n.w = 0, which no exit search accepts
+      E = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(i));
+      if (a.stats) atomicAdd(&a.stats[VORO_STAT_BAD_CSR], 1ull);
+    } else {
+      E = make_float4(a.sites[3 * (size_t)j] - px, a.sites[3 * (size_t)j + 1] - py,
+                      a.sites[3 * (size_t)j + 2] - pz, __int_as_float(j));
+    }
+    a.edges[e] = E;
+  }
+}
+
+// ------------------------------------------------------- explicit-ray launch
+struct RayArgs {
+  DevScene s;
+  WalkParams w;
+  RayMap map;
+  const float* o;
+  const float* d;
+  const float* tmax;
+  const int32_t* start;
+  // forward outputs
+  float* rgb;
+  float* T;
+  int32_t* nsteps;
+  int32_t* cells_out;
+  int max_record;
+  // backward inputs / outputs
+  const float* rgb_in;
+  const float* T_in;
+  const float* g_rgb;
+  const float* g_T;
+  Grads g;
+  unsigned long long* stats;
+};
+
+template <int LPR, int TEX>
+__global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
+  const int nwaves = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / LPR;
+  const int sub = lane % LPR;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int ray = map_ray<LPR>(a.map, lb, wave, nwaves, grp);
+  Counters cnt;
+  if (ray >= 0) {
+    RayIn r;
+    r.ox = a.o[3 * (size_t)ray];
+    r.oy = a.o[3 * (size_t)ray + 1];
+    r.oz = a.o[3 * (size_t)ray + 2];
+    r.dx = a.d[3 * (size_t)ray];
+    r.dy = a.d[3 * (size_t)ray + 1];
+    r.dz = a.d[3 * (size_t)ray + 2];
+    r.tmax = a.tmax[ray];
+    r.start = a.start[ray];
+    int32_t* rec = (a.cells_out && a.max_record > 0) ? a.cells_out + (size_t)ray * a.max_record
+                                                     : nullptr;
+    const RayOut out = walk_forward<LPR, TEX>(a.s, a.w, r, sub, rec, a.max_record, cnt);
+    if (sub == 0) {
+      a.rgb[3 * (size_t)ray] = out.r;
+      a.rgb[3 * (size_t)ray + 1] = out.g;
+      a.rgb[3 * (size_t)ray + 2] = out.b;
+      a.T[ray] = out.T;
+      if (a.nsteps) a.nsteps[ray] = out.k;
+      if (rec)
+        for (int k = out.k; k < a.max_record; ++k) rec[k] = -1;
+    }
+  }
+  if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
+}
+
+template <int LPR, int TEX>
+__global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
+  const int nwaves = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / LPR;
+  const int sub = lane % LPR;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int ray = map_ray<LPR>(a.map, lb, wave, nwaves, grp);
+  Counters cnt;
+  if (ray >= 0) {
+    RayIn r;
+    r.ox = a.o[3 * (size_t)ray];
+    r.oy = a.o[3 * (size_t)ray + 1];
+    r.oz = a.o[3 * (size_t)ray + 2];
+    r.dx = a.d[3 * (size_t)ray];
+    r.dy = a.d[3 * (size_t)ray + 1];
+    r.dz = a.d[3 * (size_t)ray + 2];
+    r.tmax = a.tmax[ray];
+    r.start = a.start[ray];
+    Upstream u;
+    u.Cr = a.rgb_in[3 * (size_t)ray];
+    u.Cg = a.rgb_in[3 * (size_t)ray + 1];
+    u.Cb = a.rgb_in[3 * (size_t)ray + 2];
+    u.Tf = a.T_in[ray];
+    u.gr = a.g_rgb[3 * (size_t)ray];
+    u.gg = a.g_rgb[3 * (size_t)ray + 1];
+    u.gb = a.g_rgb[3 * (size_t)ray + 2];
+    u.gT = a.g_T ? a.g_T[ray] : 0.0f;
+    walk_backward<LPR, TEX>(a.s, a.w, r, u, sub, a.g, cnt);
+  }
+  if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
+}
+
+template <int LPR, int TEX>
+static void launch_ray_kernel(bool backward, const RayArgs& a, int blocks, int block,
+                              hipStream_t st) {
+  if (backward)
+    hipLaunchKernelGGL((k_render_bwd<LPR, TEX>), dim3(blocks), dim3(block), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_render_fwd<LPR, TEX>), dim3(blocks), dim3(block), 0, st, a);
+}
+
+template <int TEX>
+static void dispatch_lpr(int lpr, bool backward, const RayArgs& a, int blocks, int block,
+                         hipStream_t st) {
+  switch (lpr) {
+    case 1: launch_ray_kernel<1, TEX>(backward, a, blocks, block, st); break;
+    case 2: launch_ray_kernel<2, TEX>(backward, a, blocks, block, st); break;
+    case 4: launch_ray_kernel<4, TEX>(backward, a, blocks, block, st); break;
+    case 8: launch_ray_kernel<8, TEX>(backward, a, blocks, block, st); break;
+    default: launch_ray_kernel<16, TEX>(backward, a, blocks, block, st); break;
+  }
+}
+
+static void dispatch_ray_kernel(int tex, int lpr, bool backward, const RayArgs& a, int blocks,
+                                int block, hipStream_t st) {
+  switch (tex) {
+    case VORO_TEX_F32: dispatch_lpr<VORO_TEX_F32>(lpr, backward, a, blocks, block, st); break;
+    case VORO_TEX_F16: dispatch_lpr<VORO_TEX_F16>(lpr, backward, a, blocks, block, st); break;
+    default: dispatch_lpr<VORO_TEX_BF16>(lpr, backward, a, blocks, block, st); break;
+  }
+}
+
+DevScene dev_scene(const voro_scene* s, const void* ws) {
+  const WsLayout L = ws_layout(s->n_sites, s->n_edges);
+  DevScene d;
+  d.cells = reinterpret_cast<const float4*>((const char*)ws + L.cells);
+  d.edges = reinterpret_cast<const float4*>((const char*)ws + L.edges);
+  d.texels = s->texels;
+  d.n = s->n_sites;
+  d.res = s->tex_res;
+  return d;
+}
+
+WalkParams walk_params(const voro_params* p) {
+  WalkParams w;
+  w.t_stop = p->t_stop;
+  w.skip_w = p->skip_w;
+  w.tie_window = p->tie_window;
+  w.max_steps = p->max_steps;
+  return w;
+}
+
+static voro_status ray_launch(bool backward, const voro_scene* scene, const void* ws,
+                              size_t ws_bytes, const float* o, const float* d, const float* tmax,
+                              const int32_t* start, int32_t R, const voro_params* params,
+                              RayArgs a, void* stream) {
+  voro_status st;
+  if ((st = check_scene(scene)) != VORO_OK) return st;
+  if ((st = check_ws(scene, ws, ws_bytes)) != VORO_OK) return st;
+  if ((st = check_params(params, backward)) != VORO_OK) return st;
+  if (R < 0) return fail(VORO_EINVAL, "R must be >= 0");
+  if (R == 0) return VORO_OK;
+  if (!o || !d || !tmax || !start) return fail(VORO_EINVAL, "ray arrays must not be NULL");
+  if (params->img_w > 0 && (R % params->img_w) != 0)
+    return fail(VORO_EINVAL, "R (%d) must be a multiple of img_w (%d)", R, params->img_w);
+  if ((st = check_device()) != VORO_OK) return st;
+  const Launch L = resolve_launch(params);
+  a.s = dev_scene(scene, ws);
+  a.w = walk_params(params);
+  a.o = o;
+  a.d = d;
+  a.tmax = tmax;
+  a.start = start;
+  a.map.n_rays = R;
+  a.map.img_w = params->img_w;
+  a.map.img_h = params->img_w > 0 ? R / params->img_w : 1;
+  a.map.tile_w = L.tile_w;
+  a.map.tile_h = L.tile_h;
+  const int nwaves = L.block / 64;
+  long blocks;
+  if (params->img_w > 0) {
+    const int wx = nwaves >= 2 ? 2 : 1;
+    const int bw = L.tile_w * wx;
+    const int bh = L.tile_h * (nwaves / wx);
+    a.map.blocks_x = (params->img_w + bw - 1) / bw;
+    blocks = (long)a.map.blocks_x * ((a.map.img_h + bh - 1) / bh);
+  } else {
+    a.map.blocks_x = 0;
+    const long rays_per_block = (long)L.block / L.lpr;
+    blocks = (R + rays_per_block - 1) / rays_per_block;
+  }
+  if (blocks > 0x7fffffff) return fail(VORO_EINVAL, "too many rays");
+  dispatch_ray_kernel(scene->tex_dtype, L.lpr, backward, a, (int)blocks, L.block,
+                      (hipStream_t)stream);
+  return check_launch(backward ? "voro_render_bwd" : "voro_render_fwd");
+}
+
+}  // namespace voro
+
+using namespace voro;
+
+extern "C" {
+
+voro_status voro_prepare(const voro_scene* scene, void* ws, size_t ws_bytes, uint64_t* stats,
+                         void* stream) {
+  voro_status st;
+  if ((st = check_scene(scene)) != VORO_OK) return st;
+  if ((st = check_ws(scene, ws, ws_bytes)) != VORO_OK) return st;
+  if ((st = check_device()) != VORO_OK) return st;
+  const WsLayout L = ws_layout(scene->n_sites, scene->n_edges);
+  PrepArgs a;
+  a.sites = scene->sites;
+  a.density = scene->density;
+  a.nbr_off = scene->nbr_off;
+  a.nbr_idx = scene->nbr_idx;
+  a.n = scene->n_sites;
+  a.m = (int)scene->n_edges;
+  a.cells = reinterpret_cast<float4*>((char*)ws + L.cells);
+  a.edges = reinterpret_cast<float4*>((char*)ws + L.edges);
+  a.stats = reinterpret_cast<unsigned long long*>(stats);
+  const long threads = (long)scene->n_sites * 16;
+  const int blocks = (int)((threads + 255) / 256);
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
+  return check_launch("voro_prepare");
+}
+
+voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_bytes,
+                            const float* o, const float* d, const float* tmax,
+                            const int32_t* start_cell, int32_t R, const voro_params* params,
+                            float* rgb, float* T, int32_t* nsteps, int32_t* cells,
+                            uint64_t* stats, void* stream) {
+  if (R > 0 && (!rgb || !T)) return fail(VORO_EINVAL, "rgb and T must not be NULL");
+  if (params && params->max_record > 0 && !cells)
+    return fail(VORO_EINVAL, "cells must not be NULL when max_record > 0");
+  RayArgs a = {};
+  a.rgb = rgb;
+  a.T = T;
+  a.nsteps = nsteps;
+  a.cells_out = cells;
+  a.max_record = params ? params->max_record : 0;
+  a.stats = reinterpret_cast<unsigned long long*>(stats);
+  return ray_launch(false, scene, ws, ws_bytes, o, d, tmax, start_cell, R, params, a, stream);
+}
+
+voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_bytes,
+                            const float* o, const float* d, const float* tmax,
+                            const int32_t* start_cell, int32_t R, const voro_params* params,
+                            const float* rgb, const float* T, const float* g_rgb,
+                            const float* g_T, float* g_sites, float* g_density,
+                            float* g_texels, uint64_t* stats, void* stream) {
+  if (R > 0 && (!rgb || !T || !g_rgb))
+    return fail(VORO_EINVAL, "rgb, T and g_rgb must not be NULL");
+  if (R > 0 && (!g_sites || !g_density || !g_texels))
+    return fail(VORO_EINVAL, "gradient outputs must not be NULL");
+  if (g_texels && !aligned(g_texels, 16)) return fail(VORO_EINVAL, "g_texels must be 16-byte aligned");
+  RayArgs a = {};
+  a.rgb_in = rgb;
+  a.T_in = T;
+  a.g_rgb = g_rgb;
+  a.g_T = g_T;
+  a.g.sites = g_sites;
+  a.g.density = g_density;
+  a.g.texels = g_texels;
+  a.stats = reinterpret_cast<unsigned long long*>(stats);
+  return ray_launch(true, scene, ws, ws_bytes, o, d, tmax, start_cell, R, params, a, stream);
+}
+
+}  // extern "C"

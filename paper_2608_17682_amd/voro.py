@@ -1,0 +1,434 @@
+"""ctypes binding of libvoro.so (C ABI in include/voro.h).
+
+Argument marshalling only: every function forwards device pointers of torch
+tensors, sizes and structs to the C entry point of the same name on the
+current HIP stream and raises ``VoroError`` on a non-zero status.  All
+arithmetic runs in the library's HIP kernels; when the library is missing
+the first call raises (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("VORO_LIB", os.path.join(_HERE, "libvoro.so"))
+
+VORO_OK = 0
+VORO_EINVAL = -1
+VORO_ENODEV = -2
+VORO_EHIP = -3
+VORO_EUNSUPPORTED = -4
+VORO_EWORKSPACE = -5
+
+TEX_F32, TEX_F16, TEX_BF16 = 0, 1, 2
+CAM_PINHOLE, CAM_FISHEYE, CAM_ROLLING_SHUTTER, CAM_THIN_LENS = 0, 1, 2, 3
+MAX_VIEWS = 16
+
+STAT_NAMES = ["rays", "steps", "degree_sum", "max_steps", "nan", "bad_start", "fp64_redecide",
+              "skipped", "bad_csr", "locate_cap"]
+STAT_COUNT = 16
+
+# every entry point declared in include/voro.h
+EXPORTS = [
+    "voro_version", "voro_last_error", "voro_default_params", "voro_workspace_size",
+    "voro_prepare", "voro_locate_origins", "voro_render_fwd", "voro_render_bwd",
+    "voro_camera_counts", "voro_gen_rays", "voro_render_views_fwd", "voro_render_views_bwd",
+    "voro_reorder_scratch_size", "voro_morton_reorder", "voro_cast_texels",
+]
+
+
+class VoroError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+class voro_scene(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("tex_res", ctypes.c_int32),
+                ("tex_dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("n_edges", ctypes.c_int64), ("sites", ctypes.c_void_p),
+                ("density", ctypes.c_void_p), ("nbr_off", ctypes.c_void_p),
+                ("nbr_idx", ctypes.c_void_p), ("texels", ctypes.c_void_p)]
+
+
+class voro_params(ctypes.Structure):
+    _fields_ = [("t_stop", ctypes.c_float), ("skip_w", ctypes.c_float),
+                ("max_steps", ctypes.c_int32), ("tie_window", ctypes.c_float),
+                ("appearance", ctypes.c_int32), ("lanes_per_ray", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("img_w", ctypes.c_int32), ("max_record", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class voro_camera(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
+                ("c2w", ctypes.c_float * 12), ("fov", ctypes.c_float),
+                ("tmax", ctypes.c_float), ("lens_radius", ctypes.c_float),
+                ("focus_dist", ctypes.c_float), ("rs_delta", ctypes.c_float * 3),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"libvoro.so not found at {LIB_PATH}: build it with "
+                "`python -m paper_2608_17682_amd.build` (there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        P = ctypes.POINTER
+        sig = {
+            "voro_version": ([], ctypes.c_char_p),
+            "voro_last_error": ([], ctypes.c_char_p),
+            "voro_default_params": ([P(voro_params)], i32),
+            "voro_workspace_size": ([P(voro_scene), P(ctypes.c_size_t)], i32),
+            "voro_prepare": ([P(voro_scene), vp, ctypes.c_size_t, vp, vp], i32),
+            "voro_locate_origins": ([P(voro_scene), vp, ctypes.c_size_t, vp, vp, i32, vp, vp, vp],
+                                    i32),
+            "voro_render_fwd": ([P(voro_scene), vp, ctypes.c_size_t, vp, vp, vp, vp, i32,
+                                 P(voro_params), vp, vp, vp, vp, vp, vp], i32),
+            "voro_render_bwd": ([P(voro_scene), vp, ctypes.c_size_t, vp, vp, vp, vp, i32,
+                                 P(voro_params), vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+            "voro_camera_counts": ([P(voro_camera), i32, P(i64), P(i64)], i32),
+            "voro_gen_rays": ([P(voro_camera), i32, vp, vp, vp, vp], i32),
+            "voro_render_views_fwd": ([P(voro_scene), vp, ctypes.c_size_t, P(voro_camera), i32,
+                                       P(voro_params), vp, vp, vp, vp, vp, vp], i32),
+            "voro_render_views_bwd": ([P(voro_scene), vp, ctypes.c_size_t, P(voro_camera), i32,
+                                       P(voro_params), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+                                      i32),
+            "voro_reorder_scratch_size": ([i32, i64, P(ctypes.c_size_t)], i32),
+            "voro_morton_reorder": ([P(voro_scene), P(voro_scene), vp, vp, vp, ctypes.c_size_t,
+                                     vp], i32),
+            "voro_cast_texels": ([vp, vp, i64, i32, vp], i32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != VORO_OK:
+        raise VoroError(status, where, lib().voro_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device (or host) address of a tensor, None for None."""
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    if torch.cuda.is_available():
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+def version() -> str:
+    return lib().voro_version().decode()
+
+
+def last_error() -> str:
+    return lib().voro_last_error().decode()
+
+
+# --------------------------------------------------------------- structs
+
+def default_params(**kw) -> voro_params:
+    p = voro_params()
+    _check(lib().voro_default_params(ctypes.byref(p)), "voro_default_params")
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def make_camera(model, width, height, c2w, fov, tmax, rs_delta=(0.0, 0.0, 0.0),
+                lens_radius=0.0, focus_dist=1.0, spp=1) -> voro_camera:
+    c = voro_camera()
+    c.model, c.width, c.height, c.spp = int(model), int(width), int(height), int(spp)
+    m = np.asarray(c2w, np.float64).reshape(3, 4).astype(np.float32).reshape(-1)
+    for i in range(12):
+        c.c2w[i] = float(m[i])
+    c.fov, c.tmax = float(fov), float(tmax)
+    c.lens_radius, c.focus_dist = float(lens_radius), float(focus_dist)
+    for i in range(3):
+        c.rs_delta[i] = float(rs_delta[i])
+    return c
+
+
+def camera_of(cam) -> voro_camera:
+    """voro_camera from any object with the camera-description attributes."""
+    return make_camera(cam.model, cam.width, cam.height, cam.c2w, cam.fov, cam.tmax,
+                       cam.rs_delta, cam.lens_radius, cam.focus_dist, cam.spp)
+
+
+def camera_array(cams: Sequence) -> ctypes.Array:
+    arr = (voro_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = c if isinstance(c, voro_camera) else camera_of(c)
+    return arr
+
+
+def voro_camera_counts(cams) -> tuple:
+    arr = camera_array(cams)
+    nr, npx = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().voro_camera_counts(arr, len(arr), ctypes.byref(nr), ctypes.byref(npx)),
+           "voro_camera_counts")
+    return nr.value, npx.value
+
+
+# ---------------------------------------------------------------- scene
+
+_TEX_CODE = {"float32": TEX_F32, "float16": TEX_F16, "bfloat16": TEX_BF16}
+
+
+class DeviceScene:
+    """The scene's device arrays plus its prepared workspace.
+
+    sites [N,3] f32, density [N] f32, nbr_off [N+1] i32, nbr_idx [M] i32,
+    texels [N,R,R,4] f32/f16/bf16 - all contiguous device tensors.
+    """
+
+    def __init__(self, sites, density, nbr_off, nbr_idx, texels):
+        import torch
+        self.sites = sites
+        self.density = density
+        self.nbr_off = nbr_off
+        self.nbr_idx = nbr_idx
+        self.texels = texels
+        for name in ("sites", "density", "nbr_off", "nbr_idx", "texels"):
+            t = getattr(self, name)
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+        self.tex_dtype = _TEX_CODE[str(texels.dtype).replace("torch.", "")]
+        self.ws = None
+        self.ws_bytes = 0
+        self.stats = torch.zeros(STAT_COUNT, dtype=torch.int64, device=sites.device)
+
+    @property
+    def n(self):
+        return int(self.sites.shape[0])
+
+    @property
+    def tex_res(self):
+        return int(self.texels.shape[1])
+
+    def c(self) -> voro_scene:
+        s = voro_scene()
+        s.n_sites = self.n
+        s.tex_res = self.tex_res
+        s.tex_dtype = self.tex_dtype
+        s.reserved0 = 0
+        s.n_edges = int(self.nbr_idx.shape[0])
+        s.sites = _ptr(self.sites)
+        s.density = _ptr(self.density)
+        s.nbr_off = _ptr(self.nbr_off)
+        s.nbr_idx = _ptr(self.nbr_idx) if self.nbr_idx.numel() else None
+        s.texels = _ptr(self.texels)
+        return s
+
+    def ensure_workspace(self):
+        import torch
+        nbytes = voro_workspace_size(self)
+        if self.ws is None or self.ws_bytes < nbytes:
+            # torch's caching allocator returns 256-byte aligned blocks
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.sites.device)
+            self.ws_bytes = nbytes
+        return self.ws
+
+    def with_arrays(self, **kw) -> "DeviceScene":
+        """Same scene with some arrays replaced (shares the workspace)."""
+        d = dict(sites=self.sites, density=self.density, nbr_off=self.nbr_off,
+                 nbr_idx=self.nbr_idx, texels=self.texels)
+        d.update(kw)
+        out = DeviceScene(**d)
+        out.ws, out.ws_bytes, out.stats = self.ws, self.ws_bytes, self.stats
+        return out
+
+
+def device_scene(scene, device="cuda", tex_dtype=None) -> DeviceScene:
+    """Upload a synth.Scene-like object (numpy arrays) to the device."""
+    import torch
+    tex = torch.from_numpy(np.ascontiguousarray(scene.texels)).to(device)
+    if tex_dtype is not None:
+        tex = voro_cast_texels(tex, tex_dtype)
+    return DeviceScene(
+        torch.from_numpy(np.ascontiguousarray(scene.sites, np.float32)).to(device),
+        torch.from_numpy(np.ascontiguousarray(scene.density, np.float32)).to(device),
+        torch.from_numpy(np.ascontiguousarray(scene.nbr_off, np.int32)).to(device),
+        torch.from_numpy(np.ascontiguousarray(scene.nbr_idx, np.int32)).to(device),
+        tex)
+
+
+# ------------------------------------------------------------ entry points
+
+def voro_workspace_size(ds: DeviceScene) -> int:
+    n = ctypes.c_size_t()
+    sc = ds.c()
+    _check(lib().voro_workspace_size(ctypes.byref(sc), ctypes.byref(n)), "voro_workspace_size")
+    return n.value
+
+
+def voro_prepare(ds: DeviceScene, stats=None, stream=None):
+    ds.ensure_workspace()
+    sc = ds.c()
+    _check(lib().voro_prepare(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, _ptr(stats),
+                              _stream(stream)), "voro_prepare")
+
+
+def voro_locate_origins(ds: DeviceScene, origins, hint=None, out=None, stats=None, stream=None):
+    import torch
+    U = int(origins.shape[0])
+    if out is None:
+        out = torch.empty(U, dtype=torch.int32, device=origins.device)
+    sc = ds.c()
+    _check(lib().voro_locate_origins(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, _ptr(origins),
+                                     _ptr(hint), U, _ptr(out), _ptr(stats), _stream(stream)),
+           "voro_locate_origins")
+    return out
+
+
+def voro_render_fwd(ds: DeviceScene, o, d, tmax, start, params=None, rgb=None, T=None,
+                    nsteps=None, cells=None, stats=None, stream=None):
+    import torch
+    R = int(o.shape[0])
+    p = params or default_params()
+    dev = o.device
+    rgb = torch.empty((R, 3), dtype=torch.float32, device=dev) if rgb is None else rgb
+    T = torch.empty(R, dtype=torch.float32, device=dev) if T is None else T
+    sc = ds.c()
+    _check(lib().voro_render_fwd(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, _ptr(o), _ptr(d),
+                                 _ptr(tmax), _ptr(start), R, ctypes.byref(p), _ptr(rgb), _ptr(T),
+                                 _ptr(nsteps), _ptr(cells), _ptr(stats), _stream(stream)),
+           "voro_render_fwd")
+    return rgb, T
+
+
+def voro_render_bwd(ds: DeviceScene, o, d, tmax, start, rgb, T, g_rgb, g_T=None, params=None,
+                    g_sites=None, g_density=None, g_texels=None, stats=None, stream=None):
+    import torch
+    R = int(o.shape[0])
+    p = params or default_params()
+    dev = o.device
+    if g_sites is None:
+        g_sites = torch.zeros((ds.n, 3), dtype=torch.float32, device=dev)
+    if g_density is None:
+        g_density = torch.zeros(ds.n, dtype=torch.float32, device=dev)
+    if g_texels is None:
+        g_texels = torch.zeros(tuple(ds.texels.shape), dtype=torch.float32, device=dev)
+    sc = ds.c()
+    _check(lib().voro_render_bwd(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, _ptr(o), _ptr(d),
+                                 _ptr(tmax), _ptr(start), R, ctypes.byref(p), _ptr(rgb), _ptr(T),
+                                 _ptr(g_rgb), _ptr(g_T), _ptr(g_sites), _ptr(g_density),
+                                 _ptr(g_texels), _ptr(stats), _stream(stream)),
+           "voro_render_bwd")
+    return g_sites, g_density, g_texels
+
+
+def voro_gen_rays(cams, device="cuda", stream=None):
+    import torch
+    arr = camera_array(cams)
+    nr, _ = voro_camera_counts(list(arr))
+    o = torch.empty((nr, 3), dtype=torch.float32, device=device)
+    d = torch.empty((nr, 3), dtype=torch.float32, device=device)
+    tm = torch.empty(nr, dtype=torch.float32, device=device)
+    _check(lib().voro_gen_rays(arr, len(arr), _ptr(o), _ptr(d), _ptr(tm), _stream(stream)),
+           "voro_gen_rays")
+    return o, d, tm
+
+
+def voro_render_views_fwd(ds: DeviceScene, cams, params=None, rgb=None, T=None, ray_rgbT=None,
+                          nsteps=None, stats=None, stream=None):
+    import torch
+    arr = camera_array(cams)
+    nr, npx = voro_camera_counts(list(arr))
+    dev = ds.sites.device
+    rgb = torch.empty((npx, 3), dtype=torch.float32, device=dev) if rgb is None else rgb
+    T = torch.empty(npx, dtype=torch.float32, device=dev) if T is None else T
+    if ray_rgbT is None and any(c.spp > 1 for c in arr):
+        ray_rgbT = torch.empty((nr, 4), dtype=torch.float32, device=dev)
+    p = params or default_params()
+    sc = ds.c()
+    _check(lib().voro_render_views_fwd(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, arr, len(arr),
+                                       ctypes.byref(p), _ptr(rgb), _ptr(T), _ptr(ray_rgbT),
+                                       _ptr(nsteps), _ptr(stats), _stream(stream)),
+           "voro_render_views_fwd")
+    return rgb, T, ray_rgbT
+
+
+def voro_render_views_bwd(ds: DeviceScene, cams, rgb, T, ray_rgbT, g_rgb, g_T=None, params=None,
+                          g_sites=None, g_density=None, g_texels=None, stats=None, stream=None):
+    import torch
+    arr = camera_array(cams)
+    dev = ds.sites.device
+    if g_sites is None:
+        g_sites = torch.zeros((ds.n, 3), dtype=torch.float32, device=dev)
+    if g_density is None:
+        g_density = torch.zeros(ds.n, dtype=torch.float32, device=dev)
+    if g_texels is None:
+        g_texels = torch.zeros(tuple(ds.texels.shape), dtype=torch.float32, device=dev)
+    p = params or default_params()
+    sc = ds.c()
+    _check(lib().voro_render_views_bwd(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, arr, len(arr),
+                                       ctypes.byref(p), _ptr(rgb), _ptr(T), _ptr(ray_rgbT),
+                                       _ptr(g_rgb), _ptr(g_T), _ptr(g_sites), _ptr(g_density),
+                                       _ptr(g_texels), _ptr(stats), _stream(stream)),
+           "voro_render_views_bwd")
+    return g_sites, g_density, g_texels
+
+
+def voro_reorder_scratch_size(n_sites: int, n_edges: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().voro_reorder_scratch_size(int(n_sites), int(n_edges), ctypes.byref(n)),
+           "voro_reorder_scratch_size")
+    return n.value
+
+
+def voro_morton_reorder(ds: DeviceScene, stream=None):
+    """Morton-reordered copy of the scene: (new DeviceScene, perm new->old, inv_perm old->new)."""
+    import torch
+    dev = ds.sites.device
+    out = DeviceScene(torch.empty_like(ds.sites), torch.empty_like(ds.density),
+                      torch.empty_like(ds.nbr_off), torch.empty_like(ds.nbr_idx),
+                      torch.empty_like(ds.texels))
+    perm = torch.empty(ds.n, dtype=torch.int32, device=dev)
+    inv = torch.empty(ds.n, dtype=torch.int32, device=dev)
+    nbytes = voro_reorder_scratch_size(ds.n, int(ds.nbr_idx.shape[0]))
+    scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    a, b = ds.c(), out.c()
+    _check(lib().voro_morton_reorder(ctypes.byref(a), ctypes.byref(b), _ptr(perm), _ptr(inv),
+                                     _ptr(scratch), nbytes, _stream(stream)),
+           "voro_morton_reorder")
+    return out, perm, inv
+
+
+def voro_cast_texels(tex, dtype: str, stream=None):
+    """f32 texels -> 'float16' or 'bfloat16' (round to nearest even)."""
+    import torch
+    code = _TEX_CODE[dtype]
+    tdt = {TEX_F16: torch.float16, TEX_BF16: torch.bfloat16}[code]
+    out = torch.empty(tuple(tex.shape), dtype=tdt, device=tex.device)
+    _check(lib().voro_cast_texels(_ptr(tex), _ptr(out), tex.numel(), code, _stream(stream)),
+           "voro_cast_texels")
+    return out
