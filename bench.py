@@ -1,0 +1,295 @@
+"""Throughput of the Voronoi-walk renderer on one MI355X.
+
+Workload (default): the 100k-site shell scene (70% of the sites jittered on
+the unit sphere with density 50, 30% uniform in [-2,2]^3 with density 0.01),
+8x8 FP32 octahedral texels per cell, 800x800 pinhole views (60 deg FOV) at 8
+poses evenly spaced on a radius-3 orbit, tmax 8, early stop at T < 1e-4.
+
+One step = prepare the scene records once, then render the 8 poses as 8
+frames; each frame is one voro_render_views_fwd call (camera-centre cell
+search + in-kernel ray generation + walk + compositing).  Mrays/s = rays per
+step * K / timed seconds.  Scene construction (Qhull adjacency), Morton
+reordering and texel casts are one-time preprocessing outside the timed
+region, as in the paper's viewer protocol (Sec. 6.1, App. B).
+
+Prints one JSON line.  Also reported, outside `value`: FP16/BF16-texel
+forward throughput and their error against the FP64 oracle on sampled rays,
+forward+backward throughput, the dominant kernel's algorithmic bandwidth
+against the HBM peak, and the FP64 oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_POSES = 8
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2608_17682_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def step_bytes(stats, tex_bytes, n_rays):
+    """Algorithmic bytes of a forward pass: per visited cell the cell record
+    (xyz + sigma, 16 B), its adjacency bounds (8 B), per neighbour its id and
+    position (4 + 12 B), and 4 RGBA texels; per ray 44 B of ray in / colour out."""
+    steps = float(stats["steps"])
+    deg = float(stats["degree_sum"])
+    return steps * (16 + 8 + 4 * tex_bytes) + 16.0 * deg + 44.0 * n_rays
+
+
+def stats_dict(t):
+    from paper_2608_17682_amd import voro
+    a = t.cpu().numpy()
+    return {name: int(a[i]) for i, name in enumerate(voro.STAT_NAMES)}
+
+
+def oracle_sample(scene, cam, n_rays, workers, texels=None, seed=7):
+    """FP64 oracle on n_rays rays of the 64x64 centre crop (and the GPU pixel ids)."""
+    from oracle import cameras, render
+    from paper_2608_17682_amd import synth
+    o, d, tm, _ = cameras.camera_rays_of(cam)
+    crop = synth.crop_pixels(cam, 64, 0, True)
+    pick = crop[synth.sample_pixels(len(crop), n_rays, seed)]
+    o32 = o[pick].astype(np.float32)
+    d32 = d[pick].astype(np.float32)
+    tm32 = tm[pick].astype(np.float32)
+    tex = scene.texels if texels is None else texels
+    t0 = time.perf_counter()
+    rgb, T, recs = render.render_rays_parallel(scene.sites, scene.density, tex, o32, d32, tm32,
+                                               workers=workers, chunk=max(1, n_rays // workers))
+    dt = time.perf_counter() - t0
+    return pick, rgb, T, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--lanes-per-ray", type=int, default=0)
+    ap.add_argument("--tile", type=str, default="")
+    ap.add_argument("--no-morton", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip half texels and fwd+bwd")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-rays", type=int, default=192)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(rays would shard by view or screen tile with a replicated scene; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_17682_amd import synth, voro
+
+    if args.copy_probe:
+        dev = torch.device("cuda:0")
+        n = 1 << 28  # 1 GiB of float32
+        a = torch.ones(n, device=dev)
+        b = torch.empty(n, device=dev)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "launches": 5}))
+        return
+
+    t0 = time.perf_counter()
+    scene, cams = synth.config2()
+    log(f"scene built in {time.perf_counter() - t0:.1f}s: N={scene.n} M={len(scene.nbr_idx)}")
+
+    # The oracle leg runs first, in forked worker processes, before this
+    # process touches the GPU.
+    oracle_leg = None
+    if not args.no_cpu_baseline:
+        workers = min(16, os.cpu_count() or 1)
+        oracle_leg = (workers,) + oracle_sample(scene, cams[0], args.oracle_rays, workers)
+        log(f"oracle leg: {len(oracle_leg[1])} rays in {oracle_leg[4]:.1f}s on {workers} processes")
+
+    dev = torch.device("cuda:0")
+    ds0 = voro.device_scene(scene, dev)
+    if args.no_morton:
+        ds = ds0
+    else:
+        ds, perm, inv = voro.voro_morton_reorder(ds0)
+    voro.voro_prepare(ds)
+    params = voro.default_params(lanes_per_ray=args.lanes_per_ray)
+    if args.tile:
+        tw, th = (int(x) for x in args.tile.split("x"))
+        params.tile_w, params.tile_h = tw, th
+    ccams = [voro.camera_of(c) for c in cams]
+    rays_per_frame = cams[0].n_rays
+    rays_per_step = rays_per_frame * N_POSES
+    npx = cams[0].n_pixels
+    rgb = torch.empty((npx, 3), device=dev)
+    T = torch.empty(npx, device=dev)
+
+    def frame(i, p, dscene, out_rgb=rgb, out_T=T, stats=None):
+        voro.voro_render_views_fwd(dscene, [ccams[i]], p, rgb=out_rgb, T=out_T, stats=stats)
+
+    def step(dscene, p):
+        voro.voro_prepare(dscene)
+        for i in range(N_POSES):
+            frame(i, p, dscene)
+
+    # instrumented pass (untimed): steps and degree sums for the byte model
+    st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    for i in range(N_POSES):
+        frame(i, params, ds, stats=st)
+    torch.cuda.synchronize()
+    stats = stats_dict(st)
+    log(f"stats per step: {stats}")
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    # the timed region
+    secs = timed(lambda: step(ds, params), args.steps, args.warmup)
+    ms_per_step = secs * 1e3 / args.steps
+    value = rays_per_step * args.steps / secs / 1e6
+    log(f"fwd f32: {ms_per_step:.3f} ms/step, {value:.1f} Mrays/s")
+
+    # dominant kernel: per-frame views launch timed with events on its stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(N_POSES * 3)]
+    for k, (a, b) in enumerate(ev):
+        a.record()
+        frame(k % N_POSES, params, ds)
+        b.record()
+    torch.cuda.synchronize()
+    frame_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    algo_bytes_frame = step_bytes(stats, 16, rays_per_step) / N_POSES
+    achieved = algo_bytes_frame / (frame_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_views_fwd_shell100k_800x800.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tj = json.load(f)
+        if tj.get("source_hash") == source_hash():
+            traffic = tj.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_views_fwd", "launch_ms": round(frame_ms, 4),
+                "algorithmic_bytes_per_launch": int(algo_bytes_frame),
+                "mean_cells_per_ray": round(stats["steps"] / max(1, stats["rays"]), 2),
+                "mean_degree": round(stats["degree_sum"] / max(1, stats["steps"]), 2)}
+
+    extras = {}
+    if not args.no_extras:
+        # half-precision texels (Sec. 5.6), FP32 compositing
+        for name in ("float16", "bfloat16"):
+            th = voro.voro_cast_texels(ds.texels, name)
+            dsh = ds.with_arrays(texels=th)
+            voro.voro_prepare(dsh)
+            s = timed(lambda: step(dsh, params), args.steps, args.warmup)
+            extras[f"fwd_{name}_mrays_s"] = round(rays_per_step * args.steps / s / 1e6, 2)
+        # forward + backward (replay adjoint) per frame, FP32 gradients
+        g_rgb = torch.from_numpy(synth.upstream(npx, 2, with_gT=False)[0]).to(dev)
+        gs = torch.zeros((ds.n, 3), device=dev)
+        gd = torch.zeros(ds.n, device=dev)
+        gt = torch.zeros(tuple(ds.texels.shape), device=dev)
+
+        def fb():
+            voro.voro_prepare(ds)
+            for i in range(N_POSES):
+                frame(i, params, ds)
+                voro.voro_render_views_bwd(ds, [ccams[i]], rgb, T, None, g_rgb, None, params,
+                                           gs, gd, gt)
+        s = timed(fb, max(2, args.steps // 2), 1)
+        extras["fwd_bwd_f32_mrays_s"] = round(rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
+        log(f"extras: {extras}")
+
+    cpu_baseline = None
+    if oracle_leg is not None:
+        workers, pick, rgb_o, T_o, dt = oracle_leg
+        # GPU colours of the same rays (pose 0, un-reordered scene) for the error report
+        rgb0 = torch.empty((npx, 3), device=dev)
+        T0 = torch.empty(npx, device=dev)
+        voro.voro_prepare(ds0)
+        frame(0, params, ds0, rgb0, T0)
+        rgb_h = {}
+        for name in ("float16", "bfloat16"):
+            th = voro.voro_cast_texels(ds0.texels, name)
+            dsh = ds0.with_arrays(texels=th)
+            voro.voro_prepare(dsh)
+            r_ = torch.empty((npx, 3), device=dev)
+            frame(0, params, dsh, r_, torch.empty(npx, device=dev))
+            rgb_h[name] = r_.cpu().numpy()
+        torch.cuda.synchronize()
+        err32 = np.abs(rgb0.cpu().numpy()[pick] - rgb_o)
+        extras["max_abs_err_f32_vs_oracle"] = float(err32.max())
+        for name in ("float16", "bfloat16"):
+            e = np.abs(rgb_h[name][pick] - rgb_o)
+            extras[f"max_abs_err_{name}_vs_oracle"] = float(e.max())
+            extras[f"mean_abs_err_{name}_vs_oracle"] = float(e.mean())
+        cpu_baseline = {"value": round(len(pick) / dt / 1e6, 8), "unit": "Mrays/s",
+                        "cores": workers, "kind": "oracle",
+                        "sample": f"{len(pick)} rays of the 64x64 centre crop of pose 0, "
+                                  f"FP64 brute-force walk over all {scene.n} sites, "
+                                  f"{workers} processes, {dt:.1f} s"}
+        log(f"cpu baseline: {cpu_baseline}")
+
+    out = {
+        "metric": "Mrays/s fwd and fwd+bwd at 1 MI355X (fp32 vs fp16 texels); % HBM peak",
+        "value": round(value, 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "shell100k: 100k sites (70% unit-sphere shell, sigma 50; 30% "
+                               "uniform [-2,2]^3, sigma 0.01), 8x8 f32 texels, 800x800 pinhole "
+                               "60deg, 8 orbit poses (r=3) per step, tmax 8, forward",
+                   "rays_per_step": rays_per_step, "sites": scene.n,
+                   "morton": not args.no_morton,
+                   "lanes_per_ray": args.lanes_per_ray, "tile": args.tile or "default"},
+        "roofline": roofline,
+        "cpu_baseline": cpu_baseline,
+        "extras": extras,
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

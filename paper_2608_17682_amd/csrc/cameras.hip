@@ -194,12 +194,14 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
     const int tile = next_tile(a.counters, a.total_tiles, xcd, lane, probe);
     if (tile < 0) break;
     TileRay tr;
-    if (tile_ray(a.ct, tile, grp, a.tile_w, a.tile_h, tr)) {
+    const bool has = tile_ray(a.ct, tile, grp, a.tile_w, a.tile_h, tr);
+    RayIn r = {};
+    Upstream u = {};
+    if (has) {
       bool capped = false;
-      const RayIn r = views_ray(a, tr, &capped);
+      r = views_ray(a, tr, &capped);
       const voro_camera& c = a.ct.cam[tr.view];
       const size_t p = (size_t)a.ct.pix_off[tr.view] + tr.pixel;
-      Upstream u;
       const float share = 1.0f / (float)c.spp;
       if (c.spp == 1) {
         u.Cr = a.rgb_in[3 * p];
@@ -217,8 +219,9 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
       u.gg = a.g_rgb[3 * p + 1] * share;
       u.gb = a.g_rgb[3 * p + 2] * share;
       u.gT = a.g_T ? a.g_T[p] * share : 0.0f;
-      walk_backward<LPR, TEX>(a.s, a.w, r, u, sub, a.g, cnt);
     }
+    // the whole wave walks its tile together (gradient records merge across lanes)
+    walk_backward<LPR, TEX>(a.s, a.w, r, u, has, sub, lane, a.g, cnt);
   }
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
 }

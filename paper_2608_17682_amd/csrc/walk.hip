@@ -134,8 +134,9 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int ray = map_ray<LPR>(a.map, lb, wave, nwaves, grp);
   Counters cnt;
+  RayIn r = {};
+  Upstream u = {};
   if (ray >= 0) {
-    RayIn r;
     r.ox = a.o[3 * (size_t)ray];
     r.oy = a.o[3 * (size_t)ray + 1];
     r.oz = a.o[3 * (size_t)ray + 2];
@@ -144,7 +145,6 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
     r.dz = a.d[3 * (size_t)ray + 2];
     r.tmax = a.tmax[ray];
     r.start = a.start[ray];
-    Upstream u;
     u.Cr = a.rgb_in[3 * (size_t)ray];
     u.Cg = a.rgb_in[3 * (size_t)ray + 1];
     u.Cb = a.rgb_in[3 * (size_t)ray + 2];
@@ -153,8 +153,9 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
     u.gg = a.g_rgb[3 * (size_t)ray + 1];
     u.gb = a.g_rgb[3 * (size_t)ray + 2];
     u.gT = a.g_T ? a.g_T[ray] : 0.0f;
-    walk_backward<LPR, TEX>(a.s, a.w, r, u, sub, a.g, cnt);
   }
+  // all lanes take part: the gradient records are merged across the wave
+  walk_backward<LPR, TEX>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, cnt);
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
 }
 

@@ -129,113 +129,244 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
   return out;
 }
 
-// dL/dt of the bisector crossing between cells a (left) and b (entered) at
-// parameter t, pushed to both sites: dt/dp_a = (x - p_a)/beta,
-// dt/dp_b = (p_b - x)/beta, x = o + t w, beta = (p_b - p_a).w.
-__device__ __forceinline__ void flush_face(const DevScene& s, const Grads& g, const RayIn& r,
-                                           int a, int b, float t, float coef) {
-  const float4 A = s.cells[2 * (size_t)a];
-  const float4 B = s.cells[2 * (size_t)b];
-  const float nx = B.x - A.x;
-  const float ny = B.y - A.y;
-  const float nz = B.z - A.z;
-  const float beta = dot3(nx, ny, nz, r.dx, r.dy, r.dz);
-  const float xx = fmaf(t, r.dx, r.ox);
-  const float xy = fmaf(t, r.dy, r.oy);
-  const float xz = fmaf(t, r.dz, r.oz);
-  const float c = coef / beta;
-  atomicAdd(&g.sites[3 * (size_t)a], c * (xx - A.x));
-  atomicAdd(&g.sites[3 * (size_t)a + 1], c * (xy - A.y));
-  atomicAdd(&g.sites[3 * (size_t)a + 2], c * (xz - A.z));
-  atomicAdd(&g.sites[3 * (size_t)b], c * (B.x - xx));
-  atomicAdd(&g.sites[3 * (size_t)b + 1], c * (B.y - xy));
-  atomicAdd(&g.sites[3 * (size_t)b + 2], c * (B.z - xz));
+// ------------------------------------------------------------- adjoint
+//
+// Adjoint of walk_forward for L = g.C + g_T T_final.  The walk is replayed
+// with identical decisions and, per segment k (App. X of the derivation in
+// the oracle's adjoint module):
+//   dL/dtau_k  = g.(T_{k+1} c_k - S_k) - g_T T_final,  S_k = C - sum_{j<=k} w_j c_j
+//   dL/dsigma  += dL/dtau_k delta_k,    dL/dtexel_q += w_k b_q g
+//   the exit end of the segment moves with its bisector crossing (+D) and
+//   the entry end, the crossing that last advanced t, with -D, where
+//   D = sigma_k dL/dtau_k; for the bisector of (a, b) crossed at t,
+//   dt/dp_a = (x - p_a)/beta, dt/dp_b = (p_b - x)/beta, beta = (p_b - p_a).w.
+//
+// Gradient traffic.  A visited cell receives contributions from its own
+// segment and from its two faces on the ray, i.e. from three consecutive
+// steps.  Each lane keeps a sliding window (previous cell, current cell, next
+// cell) and emits a cell's finished record - dsigma, dp (3), 12 texel terms -
+// once, one step after leaving it.  Before the atomics, the records of the
+// whole wave are merged on a butterfly: partner lanes (lane ^ m) holding the
+// same key (cell, texel quad) add up and one of them retires, so coherent
+// rays crossing the same cell issue one set of atomics instead of one per
+// lane.  Faces whose far cell has already been emitted (only after zero-length
+// segments) go straight to the atomics.
+
+__device__ __forceinline__ void atomic_site(const Grads& g, int cell, float x, float y, float z) {
+  atomicAdd(&g.sites[3 * (size_t)cell], x);
+  atomicAdd(&g.sites[3 * (size_t)cell + 1], y);
+  atomicAdd(&g.sites[3 * (size_t)cell + 2], z);
 }
 
-// Adjoint of walk_forward (replays it with identical decisions).
-//   dL/dtau_k = g.(T_{k+1} c_k - S_k) - g_T T_final, S_k = C - sum_{j<=k} w_j c_j
-//   dL/dsigma += dL/dtau_k delta_k, dL/dtexel_q += w_k b_q g,
-//   each segment end moves with its bisector: +sigma_k dL/dtau_k at the exit
-//   face, -sigma_k dL/dtau_k at the entry face (the crossing that last
-//   advanced t); a face's two contributions are summed before it is flushed.
-template <int LPR, int TEX>
-__device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParams& w,
-                                              const RayIn& r, const Upstream& u, int sub,
-                                              const Grads& g, Counters& cnt) {
-  if (!(r.tmax > 0.0f)) return;
-  if (r.start < 0 || r.start >= s.n) {
-    cnt.bad++;
-    return;
+// Merge equal-key records across the wave and issue the atomics.  Every lane
+// of the wave must call this (key < 0: no record).
+template <int LPR>
+__device__ __forceinline__ void emit_records(int key, float ds, float px, float py, float pz, float w,
+                                             const Taps& tp, const Upstream& u, int lane, int RR,
+                                             int R, const Grads& g) {
+  float v[16];
+  v[0] = ds;
+  v[1] = px;
+  v[2] = py;
+  v[3] = pz;
+  const float q[4] = {w * tp.w00, w * tp.w01, w * tp.w10, w * tp.w11};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    v[4 + 3 * t] = q[t] * u.gr;
+    v[5 + 3 * t] = q[t] * u.gg;
+    v[6 + 3 * t] = q[t] * u.gb;
   }
-  cnt.rays++;
-  const int R = s.res;
-  const Taps tp = make_taps(r.dx, r.dy, r.dz, R);
-  float T = 1.0f, Pr = 0.0f, Pg = 0.0f, Pb = 0.0f, t_in = 0.0f;
-  int cur = r.start;
-  int k = 0;
-  int fa = -1, fb = -1;
-  float ft = 0.0f, fg = 0.0f;
-  for (;;) {
-    const Cell c = load_cell(s.cells, cur);
-    const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
-    cnt.redecide += ex.redecided ? 1u : 0u;
-    cnt.deg += (uint32_t)c.deg;
-    const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
-    const float wk = T * sg.alpha;
-    float cr, cg, cb;
-    texel_rgb<TEX>(s.texels, cur, R, tp, cr, cg, cb);
-    Pr = fmaf(wk, cr, Pr);
-    Pg = fmaf(wk, cg, Pg);
-    Pb = fmaf(wk, cb, Pb);
-    const float Tn = T * sg.trans;
-    const float Sr = u.Cr - Pr;
-    const float Sg = u.Cg - Pg;
-    const float Sb = u.Cb - Pb;
-    const float dtau =
-        fmaf(u.gb, Tn * cb - Sb, fmaf(u.gg, Tn * cg - Sg, u.gr * (Tn * cr - Sr))) - u.gT * u.Tf;
-    if (sub == 0) {
-      atomicAdd(&g.density[cur], dtau * sg.delta);
-      float* tq = g.texels + ((size_t)cur * (size_t)(R * R) + (size_t)tp.base) * 4;
-      const float q00 = wk * tp.w00, q01 = wk * tp.w01, q10 = wk * tp.w10, q11 = wk * tp.w11;
-      atomicAdd(tq + 0, q00 * u.gr);
-      atomicAdd(tq + 1, q00 * u.gg);
-      atomicAdd(tq + 2, q00 * u.gb);
-      atomicAdd(tq + 4, q01 * u.gr);
-      atomicAdd(tq + 5, q01 * u.gg);
-      atomicAdd(tq + 6, q01 * u.gb);
-      float* tr = tq + 4 * R;
-      atomicAdd(tr + 0, q10 * u.gr);
-      atomicAdd(tr + 1, q10 * u.gg);
-      atomicAdd(tr + 2, q10 * u.gb);
-      atomicAdd(tr + 4, q11 * u.gr);
-      atomicAdd(tr + 5, q11 * u.gg);
-      atomicAdd(tr + 6, q11 * u.gb);
-    }
-    if (sg.delta > 0.0f) {
-      const float dd = c.sigma * dtau;
-      if (fa >= 0) fg -= dd;
-      if (ex.t < r.tmax && ex.next >= 0) {
-        if (fa >= 0 && sub == 0) flush_face(s, g, r, fa, fb, ft, fg);
-        fa = cur;
-        fb = ex.next;
-        ft = ex.t;
-        fg = dd;
+#pragma unroll
+  for (int m = LPR; m < 64; m <<= 1) {
+    const int pk = __shfl_xor(key, m);
+    const bool match = key >= 0 && pk == key;
+    if (!__any(match)) continue;
+    float pv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) pv[i] = __shfl_xor(v[i], m);
+    if (match) {
+      if ((lane & m) == 0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] += pv[i];
+      } else {
+        key = -1;
       }
     }
-    T = Tn;
-    ++k;
-    if (T < w.t_stop) break;
-    if (!(ex.t < r.tmax) || ex.next < 0) break;
-    if (k >= w.max_steps) {
-      cnt.maxsteps++;
-      break;
-    }
-    t_in = fmaxf(t_in, fminf(ex.t, r.tmax));
-    cur = ex.next;
   }
-  if (fa >= 0 && sub == 0) flush_face(s, g, r, fa, fb, ft, fg);
-  cnt.steps += (uint32_t)k;
-  if (T != T) cnt.nan++;
+  if (key >= 0) {
+    const int cell = key / RR;
+    const int base = key - cell * RR;
+    if (v[0] != 0.0f) atomicAdd(&g.density[cell], v[0]);
+    if (v[1] != 0.0f || v[2] != 0.0f || v[3] != 0.0f) atomic_site(g, cell, v[1], v[2], v[3]);
+    if (w != 0.0f || v[4] != 0.0f || v[7] != 0.0f || v[10] != 0.0f || v[13] != 0.0f) {
+      float* t0 = g.texels + ((size_t)cell * (size_t)RR + (size_t)base) * 4;
+      float* t1 = t0 + 4 * R;
+      atomicAdd(t0 + 0, v[4]);
+      atomicAdd(t0 + 1, v[5]);
+      atomicAdd(t0 + 2, v[6]);
+      atomicAdd(t0 + 4, v[7]);
+      atomicAdd(t0 + 5, v[8]);
+      atomicAdd(t0 + 6, v[9]);
+      atomicAdd(t1 + 0, v[10]);
+      atomicAdd(t1 + 1, v[11]);
+      atomicAdd(t1 + 2, v[12]);
+      atomicAdd(t1 + 4, v[13]);
+      atomicAdd(t1 + 5, v[14]);
+      atomicAdd(t1 + 6, v[15]);
+    }
+  }
+}
+
+// Every lane of the wave must call this; has_ray = false for lanes without a
+// ray.  The loop runs until every lane's walk has ended, so the record merge
+// always sees the full wave.
+template <int LPR, int TEX>
+__device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParams& w, const RayIn& r,
+                                              const Upstream& u, bool has_ray, int sub, int lane,
+                                              const Grads& g, Counters& cnt) {
+  const int R = s.res;
+  const int RR = R * R;
+  bool active = has_ray && r.tmax > 0.0f;
+  if (active && (r.start < 0 || r.start >= s.n)) {
+    cnt.bad++;
+    active = false;
+  }
+  if (active) cnt.rays++;
+  const bool lead = sub == 0;
+  const Taps tp = make_taps(r.dx, r.dy, r.dz, R);
+  float T = 1.0f, Pr = 0.0f, Pg = 0.0f, Pb = 0.0f, t_in = 0.0f;
+  int cur = active ? r.start : 0;
+  int k = 0;
+  // previous cell's record (emitted one step late)
+  int a_cell = -1;
+  float a_ds = 0.0f, a_px = 0.0f, a_py = 0.0f, a_pz = 0.0f, a_w = 0.0f;
+  // position gradient already received by the cell entered next
+  int c_cell = -1;
+  float c_px = 0.0f, c_py = 0.0f, c_pz = 0.0f;
+  // the entry face: cells (fa, fb) and dt/dp_fa, dt/dp_fb
+  int fa = -1, fb = -1;
+  float uax = 0.0f, uay = 0.0f, uaz = 0.0f, ubx = 0.0f, uby = 0.0f, ubz = 0.0f;
+  for (;;) {
+    if (!__any(active)) break;
+    int e_key = -1;
+    float e_ds = 0.0f, e_px = 0.0f, e_py = 0.0f, e_pz = 0.0f, e_w = 0.0f;
+    if (active) {
+      const Cell c = load_cell(s.cells, cur);
+      const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
+      cnt.redecide += ex.redecided ? 1u : 0u;
+      cnt.deg += (uint32_t)c.deg;
+      const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
+      const float wk = T * sg.alpha;
+      float cr, cg, cb;
+      texel_rgb<TEX>(s.texels, cur, R, tp, cr, cg, cb);
+      Pr = fmaf(wk, cr, Pr);
+      Pg = fmaf(wk, cg, Pg);
+      Pb = fmaf(wk, cb, Pb);
+      const float Tn = T * sg.trans;
+      const float Sr = u.Cr - Pr;
+      const float Sg = u.Cg - Pg;
+      const float Sb = u.Cb - Pb;
+      const float dtau =
+          fmaf(u.gb, Tn * cb - Sb, fmaf(u.gg, Tn * cg - Sg, u.gr * (Tn * cr - Sr))) - u.gT * u.Tf;
+      // this cell's record starts with what its entry face already sent it
+      float m_px = c_cell == cur ? c_px : 0.0f;
+      float m_py = c_cell == cur ? c_py : 0.0f;
+      float m_pz = c_cell == cur ? c_pz : 0.0f;
+      int n_cell = -1;
+      float n_px = 0.0f, n_py = 0.0f, n_pz = 0.0f;
+      if (sg.delta > 0.0f) {
+        const float D = c.sigma * dtau;
+        if (fa >= 0) {
+          // entry end: -D along the entry face
+          if (fa == a_cell) {
+            a_px = fmaf(-D, uax, a_px);
+            a_py = fmaf(-D, uay, a_py);
+            a_pz = fmaf(-D, uaz, a_pz);
+          } else if (lead) {
+            atomic_site(g, fa, -D * uax, -D * uay, -D * uaz);
+          }
+          if (fb == cur) {
+            m_px = fmaf(-D, ubx, m_px);
+            m_py = fmaf(-D, uby, m_py);
+            m_pz = fmaf(-D, ubz, m_pz);
+          } else if (fb == a_cell) {
+            a_px = fmaf(-D, ubx, a_px);
+            a_py = fmaf(-D, uby, a_py);
+            a_pz = fmaf(-D, ubz, a_pz);
+          } else if (lead) {
+            atomic_site(g, fb, -D * ubx, -D * uby, -D * ubz);
+          }
+        }
+        if (ex.t < r.tmax && ex.next >= 0) {
+          // exit end: +D along the exit face (cur -> next)
+          const float4 pn = s.cells[2 * (size_t)ex.next];
+          const float nx = pn.x - c.px;
+          const float ny = pn.y - c.py;
+          const float nz = pn.z - c.pz;
+          const float beta = dot3(nx, ny, nz, r.dx, r.dy, r.dz);
+          const float xx = fmaf(ex.t, r.dx, r.ox);
+          const float xy = fmaf(ex.t, r.dy, r.oy);
+          const float xz = fmaf(ex.t, r.dz, r.oz);
+          const float ib = 1.0f / beta;
+          uax = (xx - c.px) * ib;
+          uay = (xy - c.py) * ib;
+          uaz = (xz - c.pz) * ib;
+          ubx = (pn.x - xx) * ib;
+          uby = (pn.y - xy) * ib;
+          ubz = (pn.z - xz) * ib;
+          fa = cur;
+          fb = ex.next;
+          m_px = fmaf(D, uax, m_px);
+          m_py = fmaf(D, uay, m_py);
+          m_pz = fmaf(D, uaz, m_pz);
+          n_cell = ex.next;
+          n_px = D * ubx;
+          n_py = D * uby;
+          n_pz = D * ubz;
+        }
+      }
+      // the previous cell is complete: emit it
+      if (lead && a_cell >= 0) {
+        e_key = a_cell * RR + tp.base;
+        e_ds = a_ds;
+        e_px = a_px;
+        e_py = a_py;
+        e_pz = a_pz;
+        e_w = a_w;
+      }
+      a_cell = cur;
+      a_ds = dtau * sg.delta;
+      a_px = m_px;
+      a_py = m_py;
+      a_pz = m_pz;
+      a_w = wk;
+      c_cell = n_cell;
+      c_px = n_px;
+      c_py = n_py;
+      c_pz = n_pz;
+      T = Tn;
+      ++k;
+      bool stop = T < w.t_stop || !(ex.t < r.tmax) || ex.next < 0;
+      if (!stop && k >= w.max_steps) {
+        cnt.maxsteps++;
+        stop = true;
+      }
+      if (stop) {
+        active = false;
+        cnt.steps += (uint32_t)k;
+        if (T != T) cnt.nan++;
+      } else {
+        t_in = fmaxf(t_in, fminf(ex.t, r.tmax));
+        cur = ex.next;
+      }
+    }
+    emit_records<LPR>(e_key, e_ds, e_px, e_py, e_pz, e_w, tp, u, lane, RR, R, g);
+  }
+  // the last visited cell, and the unvisited cell behind an early-stopped ray's exit face
+  emit_records<LPR>(lead && a_cell >= 0 ? a_cell * RR + tp.base : -1, a_ds, a_px, a_py, a_pz, a_w,
+                    tp, u, lane, RR, R, g);
+  emit_records<LPR>(lead && c_cell >= 0 ? c_cell * RR + tp.base : -1, 0.0f, c_px, c_py, c_pz, 0.0f,
+                    tp, u, lane, RR, R, g);
 }
 
 }  // namespace voro
