@@ -100,7 +100,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rays would shard by view or screen tile with a replicated scene; see DESIGN.md)",
+              "(rays would shard by view or screen tile with a replicated scene)",
               file=sys.stderr)
         sys.exit(2)
 
