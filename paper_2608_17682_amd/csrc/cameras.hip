@@ -87,38 +87,48 @@ __global__ void k_views_setup(Centers c, float* dst, int n, unsigned int* ctr) {
   if (i < kXcd) ctr[i] = 0u;
 }
 
-// next tile for this wave, or -1 when every XCD's range is drained
-__device__ __forceinline__ int next_tile(unsigned int* counters, int total, int xcd, int lane,
-                                         int& probe) {
+// Next work unit from the XCD-partitioned queue (one thread asks), or -1
+// when every XCD's range is drained.  probe: how many ranges this caller has
+// found empty so far.
+__device__ __forceinline__ int next_unit(unsigned int* counters, int total, int xcd, int& probe) {
   while (probe < kXcd) {
     const int x = (xcd + probe) % kXcd;
     const int lo = (int)(((long)total * x) / kXcd);
     const int hi = (int)(((long)total * (x + 1)) / kXcd);
-    int t = 0;
-    if (lane == 0) t = (int)atomicAdd(&counters[x], 1u);
-    t = __shfl(t, 0);
+    const int t = (int)atomicAdd(&counters[x], 1u);
     if (lo + t < hi) return lo + t;
     ++probe;
   }
   return -1;
 }
 
+// per-wave claim: lane 0 asks, the wave shares the answer
+__device__ __forceinline__ int next_tile(unsigned int* counters, int total, int xcd, int lane,
+                                         int& probe) {
+  int t = 0;
+  if (lane == 0) t = next_unit(counters, total, xcd, probe);
+  return __shfl(t, 0);
+}
+
 struct TileRay {
   int view, px, py, s, ray, pixel;
 };
 
-// decode (tile, lane group) into a ray; returns false outside the view
-__device__ __forceinline__ bool tile_ray(const CamTable& ct, int tile, int grp, int tile_w,
-                                         int tile_h, TileRay& tr) {
-  const int v = find_view(ct.tile_off, ct.V, tile);
+// Decode (work unit, wave's sub-tile, lane group) into a ray; false outside
+// the view.  A unit is unit_w x unit_h rays; the wave covers the tile_w x
+// tile_h sub-tile at (sx, sy) tiles inside it.
+__device__ __forceinline__ bool tile_ray(const CamTable& ct, int unit, int sx, int sy, int grp,
+                                         int tile_w, int tile_h, int unit_w, int unit_h,
+                                         TileRay& tr) {
+  const int v = find_view(ct.tile_off, ct.V, unit);
   const voro_camera& c = ct.cam[v];
   const int g = ct.g[v];
   const int gw = c.width * g;
   const int gh = c.height * g;
-  const int tiles_x = (gw + tile_w - 1) / tile_w;
-  const int local = tile - ct.tile_off[v];
-  const int X = (local % tiles_x) * tile_w + grp % tile_w;
-  const int Y = (local / tiles_x) * tile_h + grp / tile_w;
+  const int units_x = (gw + unit_w - 1) / unit_w;
+  const int local = unit - ct.tile_off[v];
+  const int X = (local % units_x) * unit_w + sx * tile_w + grp % tile_w;
+  const int Y = (local / units_x) * unit_h + sy * tile_h + grp / tile_w;
   if (X >= gw || Y >= gh) return false;
   tr.view = v;
   tr.px = X / g;
@@ -154,7 +164,7 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
     const int tile = next_tile(a.counters, a.total_tiles, xcd, lane, probe);
     if (tile < 0) break;
     TileRay tr;
-    if (tile_ray(a.ct, tile, grp, a.tile_w, a.tile_h, tr)) {
+    if (tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr)) {
       bool capped = false;
       const RayIn r = views_ray(a, tr, &capped);
       capped_n += capped ? 1u : 0u;
@@ -182,19 +192,36 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
   }
 }
 
+// Backward work unit: a workgroup tile (the waves' tiles side by side, 2
+// wide), walked by the whole workgroup into one LDS gradient table that is
+// flushed to global memory before the next unit.
 template <int LPR, int TEX>
 __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int wx = nwaves >= 2 ? 2 : 1;
   const int grp = lane / LPR;
   const int sub = lane % LPR;
   const int xcd = blockIdx.x % kXcd;
+  const int unit_w = a.tile_w * wx;
+  const int unit_h = a.tile_h * (nwaves / wx);
+  const int RR = a.s.res * a.s.res;
+  __shared__ int s_keys[kTableCap];
+  __shared__ float s_vals[16 * kTableCap];
+  __shared__ int s_unit;
+  const GradTable tab{s_keys, s_vals};
+  table_clear(tab);
   Counters cnt;
   int probe = 0;
   for (;;) {
-    const int tile = next_tile(a.counters, a.total_tiles, xcd, lane, probe);
-    if (tile < 0) break;
+    if (threadIdx.x == 0) s_unit = next_unit(a.counters, a.total_tiles, xcd, probe);
+    __syncthreads();
+    const int unit = s_unit;
+    if (unit < 0) break;
     TileRay tr;
-    const bool has = tile_ray(a.ct, tile, grp, a.tile_w, a.tile_h, tr);
+    const bool has = tile_ray(a.ct, unit, wave % wx, wave / wx, grp, a.tile_w, a.tile_h, unit_w,
+                              unit_h, tr);
     RayIn r = {};
     Upstream u = {};
     if (has) {
@@ -221,7 +248,10 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
       u.gT = a.g_T ? a.g_T[p] * share : 0.0f;
     }
     // the whole wave walks its tile together (gradient records merge across lanes)
-    walk_backward<LPR, TEX>(a.s, a.w, r, u, has, sub, lane, a.g, cnt);
+    walk_backward<LPR, TEX>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, cnt);
+    __syncthreads();
+    table_flush(tab, a.g, RR, a.s.res);
+    __syncthreads();
   }
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
 }
@@ -339,7 +369,11 @@ static voro_status views_common(bool backward, const voro_scene* scene, void* ws
   a.center_cell = centers;
   a.s = dev_scene(scene, ws);
   a.w = walk_params(params);
-  a.ct = make_table(cams, V, L.tile_w, L.tile_h);
+  // forward work units are wave tiles, backward units workgroup tiles
+  const int nw = L.block / 64;
+  const int wxu = nw >= 2 ? 2 : 1;
+  a.ct = backward ? make_table(cams, V, L.tile_w * wxu, L.tile_h * (nw / wxu))
+                  : make_table(cams, V, L.tile_w, L.tile_h);
   a.total_tiles = a.ct.tile_off[V];
   a.tile_w = L.tile_w;
   a.tile_h = L.tile_h;

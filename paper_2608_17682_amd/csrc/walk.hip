@@ -154,8 +154,16 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
     u.gb = a.g_rgb[3 * (size_t)ray + 2];
     u.gT = a.g_T ? a.g_T[ray] : 0.0f;
   }
-  // all lanes take part: the gradient records are merged across the wave
-  walk_backward<LPR, TEX>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, cnt);
+  __shared__ int s_keys[kTableCap];
+  __shared__ float s_vals[16 * kTableCap];
+  const GradTable tab{s_keys, s_vals};
+  table_clear(tab);
+  __syncthreads();
+  // all lanes take part: the gradient records are merged across the wave,
+  // then across the workgroup in the LDS table
+  walk_backward<LPR, TEX>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, cnt);
+  __syncthreads();
+  table_flush(tab, a.g, a.s.res * a.s.res, a.s.res);
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
 }
 

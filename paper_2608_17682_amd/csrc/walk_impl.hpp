@@ -158,12 +158,101 @@ __device__ __forceinline__ void atomic_site(const Grads& g, int cell, float x, f
   atomicAdd(&g.sites[3 * (size_t)cell + 2], z);
 }
 
-// Merge equal-key records across the wave and issue the atomics.  Every lane
-// of the wave must call this (key < 0: no record).
+// The 16 gradient terms of one cell record: dsigma, dp (3), and the 12 texel
+// terms w b_q g_c of its 4 taps x RGB.
+__device__ __forceinline__ void global_record(const Grads& g, int key, const float* v, int RR,
+                                              int R) {
+  const int cell = key / RR;
+  const int base = key - cell * RR;
+  if (v[0] != 0.0f) atomicAdd(&g.density[cell], v[0]);
+  if (v[1] != 0.0f || v[2] != 0.0f || v[3] != 0.0f) atomic_site(g, cell, v[1], v[2], v[3]);
+  bool tex = false;
+#pragma unroll
+  for (int i = 4; i < 16; ++i) tex = tex || v[i] != 0.0f;
+  if (tex) {
+    float* t0 = g.texels + ((size_t)cell * (size_t)RR + (size_t)base) * 4;
+    float* t1 = t0 + 4 * R;
+    atomicAdd(t0 + 0, v[4]);
+    atomicAdd(t0 + 1, v[5]);
+    atomicAdd(t0 + 2, v[6]);
+    atomicAdd(t0 + 4, v[7]);
+    atomicAdd(t0 + 5, v[8]);
+    atomicAdd(t0 + 6, v[9]);
+    atomicAdd(t1 + 0, v[10]);
+    atomicAdd(t1 + 1, v[11]);
+    atomicAdd(t1 + 2, v[12]);
+    atomicAdd(t1 + 4, v[13]);
+    atomicAdd(t1 + 5, v[14]);
+    atomicAdd(t1 + 6, v[15]);
+  }
+}
+
+// Workgroup gradient table in LDS: open addressing on the record key
+// (cell * R^2 + texel quad), 16 FP32 sums per entry stored term-major so
+// that lanes adding to different entries hit different banks.  Records are
+// added with LDS float atomics while the workgroup walks its rays; every
+// entry then reaches global memory once, when the workgroup flushes.  A
+// record that finds no slot within kTableProbes goes straight to global
+// memory.
+constexpr int kTableBits = 9;
+constexpr int kTableCap = 1 << kTableBits;
+constexpr int kTableProbes = 8;
+
+struct GradTable {
+  int* keys;    // [kTableCap], -1 = empty
+  float* vals;  // [16][kTableCap]
+};
+
+// all threads of the workgroup; needs a barrier before the table is used
+__device__ __forceinline__ void table_clear(const GradTable& t) {
+  for (int i = threadIdx.x; i < kTableCap; i += blockDim.x) {
+    t.keys[i] = -1;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) t.vals[c * kTableCap + i] = 0.0f;
+  }
+}
+
+__device__ __forceinline__ bool table_add(const GradTable& t, int key, const float* v) {
+  const unsigned h = ((unsigned)key * 2654435761u) >> (32 - kTableBits);
+  for (int p = 0; p < kTableProbes; ++p) {
+    const int slot = (int)((h + (unsigned)p) & (kTableCap - 1));
+    int k = __hip_atomic_load(&t.keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == -1) k = atomicCAS(&t.keys[slot], -1, key);
+    if (k == -1 || k == key) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (v[c] != 0.0f) atomicAdd(&t.vals[c * kTableCap + slot], v[c]);
+      return true;
+    }
+  }
+  return false;
+}
+
+// all threads of the workgroup, after a barrier: every entry to global
+// memory once, and the table left empty (a barrier must follow)
+__device__ __forceinline__ void table_flush(const GradTable& t, const Grads& g, int RR, int R) {
+  for (int i = threadIdx.x; i < kTableCap; i += blockDim.x) {
+    const int key = t.keys[i];
+    if (key < 0) continue;
+    float v[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      v[c] = t.vals[c * kTableCap + i];
+      t.vals[c * kTableCap + i] = 0.0f;
+    }
+    t.keys[i] = -1;
+    global_record(g, key, v, RR, R);
+  }
+}
+
+// Merge equal-key records of butterfly partners across the wave (lane ^ m
+// for m = LPR .. 32), then add the survivors to the workgroup table (or, with
+// no table, to global memory).  Every lane of the wave must call this (key <
+// 0: no record).
 template <int LPR>
 __device__ __forceinline__ void emit_records(int key, float ds, float px, float py, float pz, float w,
                                              const Taps& tp, const Upstream& u, int lane, int RR,
-                                             int R, const Grads& g) {
+                                             int R, const Grads& g, const GradTable* tab) {
   float v[16];
   v[0] = ds;
   v[1] = px;
@@ -194,26 +283,7 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
     }
   }
   if (key >= 0) {
-    const int cell = key / RR;
-    const int base = key - cell * RR;
-    if (v[0] != 0.0f) atomicAdd(&g.density[cell], v[0]);
-    if (v[1] != 0.0f || v[2] != 0.0f || v[3] != 0.0f) atomic_site(g, cell, v[1], v[2], v[3]);
-    if (w != 0.0f || v[4] != 0.0f || v[7] != 0.0f || v[10] != 0.0f || v[13] != 0.0f) {
-      float* t0 = g.texels + ((size_t)cell * (size_t)RR + (size_t)base) * 4;
-      float* t1 = t0 + 4 * R;
-      atomicAdd(t0 + 0, v[4]);
-      atomicAdd(t0 + 1, v[5]);
-      atomicAdd(t0 + 2, v[6]);
-      atomicAdd(t0 + 4, v[7]);
-      atomicAdd(t0 + 5, v[8]);
-      atomicAdd(t0 + 6, v[9]);
-      atomicAdd(t1 + 0, v[10]);
-      atomicAdd(t1 + 1, v[11]);
-      atomicAdd(t1 + 2, v[12]);
-      atomicAdd(t1 + 4, v[13]);
-      atomicAdd(t1 + 5, v[14]);
-      atomicAdd(t1 + 6, v[15]);
-    }
+    if (!(tab && table_add(*tab, key, v))) global_record(g, key, v, RR, R);
   }
 }
 
@@ -223,7 +293,8 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
 template <int LPR, int TEX>
 __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParams& w, const RayIn& r,
                                               const Upstream& u, bool has_ray, int sub, int lane,
-                                              const Grads& g, Counters& cnt) {
+                                              const Grads& g, const GradTable* tab,
+                                              Counters& cnt) {
   const int R = s.res;
   const int RR = R * R;
   bool active = has_ray && r.tmax > 0.0f;
@@ -360,13 +431,13 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         cur = ex.next;
       }
     }
-    emit_records<LPR>(e_key, e_ds, e_px, e_py, e_pz, e_w, tp, u, lane, RR, R, g);
+    emit_records<LPR>(e_key, e_ds, e_px, e_py, e_pz, e_w, tp, u, lane, RR, R, g, tab);
   }
   // the last visited cell, and the unvisited cell behind an early-stopped ray's exit face
   emit_records<LPR>(lead && a_cell >= 0 ? a_cell * RR + tp.base : -1, a_ds, a_px, a_py, a_pz, a_w,
-                    tp, u, lane, RR, R, g);
+                    tp, u, lane, RR, R, g, tab);
   emit_records<LPR>(lead && c_cell >= 0 ? c_cell * RR + tp.base : -1, 0.0f, c_px, c_py, c_pz, 0.0f,
-                    tp, u, lane, RR, R, g);
+                    tp, u, lane, RR, R, g, tab);
 }
 
 }  // namespace voro
