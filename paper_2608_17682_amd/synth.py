@@ -115,6 +115,13 @@ def delaunay_csr(sites: np.ndarray):
     return off.astype(np.int32), idx.astype(np.int32)
 
 
+def adjacency(sites: np.ndarray):
+    """delaunay_csr for small inputs, the parallel certified build above 300k sites."""
+    if len(sites) > 300_000:
+        return delaunay_csr_parallel(sites)
+    return delaunay_csr(sites)
+
+
 def _texels(rng, n, res):
     tex = np.zeros((n, res, res, 4), np.float32)
     tex[..., :3] = rng.uniform(0.0, 1.0, (n, res, res, 3)).astype(np.float32)
@@ -151,7 +158,7 @@ def scene_shell(n=100_000, tex_res=8, seed=2, shell_frac=0.7, with_csr=True) -> 
     sites = np.concatenate([shell, bg]).astype(np.float32)
     density = np.concatenate([np.full(n_shell, 50.0), np.full(n - n_shell, 0.01)]).astype(np.float32)
     tex = _texels(rng, n, tex_res)
-    off, idx = delaunay_csr(sites) if with_csr else (None, None)
+    off, idx = adjacency(sites) if with_csr else (None, None)
     return Scene(sites, density, tex, off, idx, name=f"shell{n}")
 
 
@@ -178,7 +185,7 @@ def scene_ellipsoids(n_surface=1_800_000, n_background=200_000, n_ell=20, tex_re
     sites = np.concatenate(pts + [bg]).astype(np.float32)
     density = np.concatenate([np.full(n_surf, 50.0), np.full(n_background, 0.01)]).astype(np.float32)
     tex = _texels(rng, sites.shape[0], tex_res)
-    off, idx = delaunay_csr(sites) if with_csr else (None, None)
+    off, idx = adjacency(sites) if with_csr else (None, None)
     return Scene(sites, density, tex, off, idx, name=f"ellipsoids{sites.shape[0]}"), ells, rng
 
 
@@ -314,3 +321,274 @@ def texels_rgb(n: int, res: int, rgb) -> np.ndarray:
     tex = np.zeros((n, res, res, 4), np.float32)
     tex[..., :3] = np.asarray(rgb, np.float32)
     return tex
+
+
+# --------------------------------------------- parallel certified adjacency
+#
+# Qhull is single threaded (~30k sites/s).  For the 2M/4M-site scenes the
+# adjacency is built on overlapping blocks in worker processes.  A point's
+# neighbour set from the local triangulation of a block's points plus a halo
+# is accepted only with a certificate: every local Delaunay tetrahedron
+# around the point has an empty circumsphere with respect to *all* sites -
+# either the sphere lies inside the region whose sites the block holds (the
+# block grown by the halo, unbounded on sides beyond every site), or a k-d
+# tree over all sites finds none strictly inside it.  Certified tetrahedra
+# are global Delaunay tetrahedra, and a point's full star of them is its
+# global star.  Points without a certificate are retried with a doubled halo.
+
+_ADJ_TREE = None
+_ADJ_HULL = None   # set of sorted global convex-hull facets (vertex-id triples)
+
+
+def _circumspheres(pts, simp):
+    a = pts[simp[:, 0]]
+    A = 2.0 * (pts[simp[:, 1:]] - a[:, None, :])                    # [T,3,3]
+    b = np.sum(pts[simp[:, 1:]] ** 2, axis=2) - np.sum(a * a, axis=1)[:, None]
+    with np.errstate(all="ignore"):
+        det = np.linalg.det(A)
+        ok = np.abs(det) > 1e-300
+        c = np.full(a.shape, np.inf)
+        if np.any(ok):
+            c[ok] = np.linalg.solve(A[ok], b[ok][..., None])[..., 0]
+        r = np.linalg.norm(c - a, axis=1)
+    r[~np.isfinite(r)] = np.inf
+    return c, r
+
+
+def _block_job(args):
+    (pts, gidx, owned, lo, hi, open_lo, open_hi) = args
+    from scipy.spatial import Delaunay
+    tri = Delaunay(pts)
+    simp = tri.simplices
+    # only tetrahedra around owned points matter
+    simp = simp[np.any(owned[simp], axis=1)]
+    c, r = _circumspheres(pts, simp)
+    finite = np.isfinite(r)
+    inside = finite.copy()
+    for ax in range(3):
+        if not open_lo[ax]:
+            inside &= (c[:, ax] - r) >= lo[ax]
+        if not open_hi[ax]:
+            inside &= (c[:, ax] + r) <= hi[ax]
+    check = np.nonzero(finite & ~inside)[0]
+    certified = inside.copy()
+    if len(check):
+        cnt = _ADJ_TREE.query_ball_point(c[check], r[check] * (1.0 - 1e-10), return_length=True)
+        certified[check] = np.asarray(cnt) == 0
+    bad = np.bincount(simp[~certified].ravel(), minlength=len(pts)) > 0
+    # where to look next: the rejected spheres hold the sites this star lacks
+    need_lo = np.full((len(pts), 3), np.inf)
+    need_hi = np.full((len(pts), 3), -np.inf)
+    rej = np.nonzero(~certified & np.isfinite(r))[0]
+    for k in range(4):
+        np.minimum.at(need_lo, simp[rej, k], c[rej] - r[rej, None])
+        np.maximum.at(need_hi, simp[rej, k], c[rej] + r[rej, None])
+    # a vertex of the local hull has a star cut open by its hull faces: it is
+    # complete only where those faces are facets of the global hull too
+    for f in tri.convex_hull:
+        if not np.any(owned[f]):
+            continue
+        key = tuple(sorted(int(x) for x in gidx[f]))
+        if key not in _ADJ_HULL:
+            bad[f] = True
+    indptr, indices = tri.vertex_neighbor_vertices
+    ok = np.nonzero(owned & ~bad)[0]
+    deg = indptr[ok + 1] - indptr[ok]
+    take = np.concatenate([np.arange(indptr[i], indptr[i + 1]) for i in ok]) if len(ok) else \
+        np.zeros(0, np.int64)
+    fl = np.nonzero(owned & bad)[0]
+    return gidx[ok], deg, gidx[indices[take]], gidx[fl], need_lo[fl], need_hi[fl]
+
+
+def delaunay_csr_parallel(sites: np.ndarray, blocks_per_axis: int = 4, workers: int = None,
+                          halo: float = None, max_rounds: int = 8, verbose: bool = False):
+    """Same CSR as delaunay_csr (rows sorted), built on overlapping blocks in
+    parallel worker processes with a per-point certificate (see above)."""
+    import multiprocessing as mp
+    import os
+    import time
+    pts = np.asarray(sites, np.float64)
+    n = len(pts)
+    workers = workers or min(16, os.cpu_count() or 1)
+    glo, ghi = pts.min(0), pts.max(0)
+    ext = np.maximum(ghi - glo, 1e-300)
+    B = blocks_per_axis
+    h = halo if halo is not None else 0.15 * float(ext.max()) / B
+    cell = np.minimum(((pts - glo) / ext * B).astype(np.int64), B - 1)
+    bid = (cell[:, 0] * B + cell[:, 1]) * B + cell[:, 2]
+    todo = [(b, ix) for b in range(B ** 3) for ix in [np.nonzero(bid == b)[0]] if len(ix)]
+    deg = np.zeros(n, np.int64)
+    parts = []
+    done = np.zeros(n, bool)
+
+    # fork workers (they share the k-d tree): call this only from a process
+    # that has not touched the GPU (scene_cached runs it in a child process)
+    global _ADJ_TREE, _ADJ_HULL
+    from scipy.spatial import ConvexHull, cKDTree
+    _ADJ_TREE = cKDTree(pts)
+    _ADJ_HULL = {tuple(sorted(int(x) for x in f)) for f in ConvexHull(pts).simplices}
+
+    # Every job also holds the global hull vertices: sites just inside the
+    # hull lie under hull facets whose far vertices are their neighbours.
+    hull_vertices = np.unique(np.array(sorted(_ADJ_HULL), np.int64).ravel())
+
+    def region_job(own, lo, hi):
+        # sites in the box [lo, hi] (k-d tree, Chebyshev ball, then trimmed)
+        ctr, half = 0.5 * (lo + hi), 0.5 * (hi - lo)
+        cand = np.asarray(_ADJ_TREE.query_ball_point(ctr, float(half.max()) * (1 + 1e-12), p=np.inf),
+                          np.int64)
+        cand = cand[np.all((pts[cand] >= lo) & (pts[cand] <= hi), axis=1)]
+        sel = np.union1d(cand, np.union1d(hull_vertices, own))
+        owned = np.zeros(len(sel), bool)
+        owned[np.searchsorted(sel, own)] = True
+        return (pts[sel], sel, owned, lo, hi, lo <= glo, hi >= ghi)
+
+    def block_job(b, own):
+        bx, by, bz = b // (B * B), (b // B) % B, b % B
+        blo = glo + ext * np.array([bx, by, bz]) / B
+        bhi = glo + ext * np.array([bx + 1, by + 1, bz + 1]) / B
+        return region_job(own, np.maximum(blo - h, glo - h), np.minimum(bhi + h, ghi + h))
+
+    # span of the global hull facets around each hull vertex: a hull
+    # vertex's neighbours can lie anywhere on those facets
+    hull_span = {}
+    for f in _ADJ_HULL:
+        fp = pts[list(f)]
+        for v in f:
+            lo_, hi_ = hull_span.get(v, (fp.min(0), fp.max(0)))
+            hull_span[v] = (np.minimum(lo_, fp.min(0)), np.maximum(hi_, fp.max(0)))
+
+    def point_region(i, nlo, nhi):
+        lo, hi = pts[i] - h, pts[i] + h
+        if i in hull_span:
+            lo, hi = np.minimum(lo, hull_span[i][0] - h), np.maximum(hi, hull_span[i][1] + h)
+        lo = np.maximum(np.minimum(lo, nlo), glo - h)
+        hi = np.minimum(np.maximum(hi, nhi), ghi + h)
+        return lo, hi
+
+    def group_jobs(failed):
+        # stragglers close together share one job whose region covers all of theirs
+        G = 4 * B
+        key = {}
+        for i, nlo, nhi in failed:
+            g = tuple(np.minimum(((pts[i] - glo) / ext * G).astype(np.int64), G - 1))
+            lo, hi = point_region(i, nlo, nhi)
+            if g in key:
+                ids, glo_, ghi_ = key[g]
+                ids.append(i)
+                key[g] = (ids, np.minimum(glo_, lo), np.maximum(ghi_, hi))
+            else:
+                key[g] = ([i], lo, hi)
+        return [region_job(np.array(sorted(ids), np.int64), lo, hi) for ids, lo, hi in key.values()]
+
+    # Sites near a face of the bounding box have long, flat Delaunay
+    # tetrahedra (nothing lies beyond the face), so each face gets one slab
+    # job spanning the whole face; interior blocks own the remaining sites.
+    dist = np.minimum(pts - glo, ghi - pts)                  # [n,3]
+    face_axis = np.argmin(dist, axis=1)
+    near = dist[np.arange(n), face_axis] < 2.0 * h
+    side_hi = (ghi - pts)[np.arange(n), face_axis] < (pts - glo)[np.arange(n), face_axis]
+    jobs = []
+    for ax in range(3):
+        for hi_side in (False, True):
+            own = np.nonzero(near & (face_axis == ax) & (side_hi == hi_side))[0]
+            if not len(own):
+                continue
+            lo, hi = glo - h, ghi + h
+            if hi_side:
+                lo = lo.copy()
+                lo[ax] = ghi[ax] - 4.0 * h
+            else:
+                hi = hi.copy()
+                hi[ax] = glo[ax] + 4.0 * h
+            jobs.append(region_job(own, lo, hi))
+    for b, own in todo:
+        own = own[~near[own]]
+        if len(own):
+            jobs.append(block_job(b, own))
+
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        for rnd in range(max_rounds):
+            t0 = time.perf_counter()
+            results = pool.map(_block_job, jobs)
+            failed = []
+            for ids, dg, nb, bad, nlo, nhi in results:
+                deg[ids] = dg
+                done[ids] = True
+                parts.append((ids, dg, nb))
+                failed.extend(zip(bad.tolist(), nlo, nhi))
+            if verbose:
+                print(f"[adjacency] round {rnd}: {len(jobs)} jobs, halo {h:.3f}, "
+                      f"{len(failed)} uncertified, {time.perf_counter() - t0:.1f}s", flush=True)
+            if not failed:
+                break
+            # the few uncertified points: one region each, covering the
+            # spheres that rejected them; the halo doubles in case that fails
+            h *= 2.0
+            jobs = group_jobs(failed)
+        else:
+            raise RuntimeError("adjacency certificate did not converge")
+    _ADJ_TREE = None
+    _ADJ_HULL = None
+    if not done.all():
+        raise RuntimeError("adjacency incomplete")
+    off = np.zeros(n + 1, np.int64)
+    np.cumsum(deg, out=off[1:])
+    if off[-1] >= 2 ** 31:
+        raise ValueError("adjacency too large for int32 offsets")
+    idx = np.empty(off[-1], np.int64)
+    for ids, dg, nb in parts:
+        src = np.concatenate([[0], np.cumsum(dg)])
+        for k, i in enumerate(ids):
+            idx[off[i]:off[i + 1]] = np.sort(nb[src[k]:src[k + 1]])
+    return off.astype(np.int32), idx.astype(np.int32)
+
+
+# ------------------------------------------------------------ scene cache
+
+def _build_config(name: str) -> Scene:
+    if name == "config2":
+        return config2()[0]
+    if name == "config3":
+        return config3(with_csr=True)[0]
+    if name == "config5":
+        return config5()[0]
+    if name.startswith("shell"):
+        return scene_shell(int(name[5:]), 8, seed=5)
+    raise ValueError(name)
+
+
+def save_scene(scene: Scene, path: str):
+    np.savez(path, sites=scene.sites, density=scene.density, texels=scene.texels,
+             nbr_off=scene.nbr_off, nbr_idx=scene.nbr_idx, name=np.array(scene.name))
+
+
+def load_scene(path: str) -> Scene:
+    z = np.load(path, allow_pickle=False)
+    return Scene(z["sites"], z["density"], z["texels"], z["nbr_off"], z["nbr_idx"],
+                 name=str(z["name"]))
+
+
+def scene_cached(name: str, cache_dir: str = None) -> Scene:
+    """A named scene (config2, config3, config5, shell<N>) from an .npz cache,
+    built on a miss by a child process (so the caller may already hold the GPU:
+    the parallel adjacency build forks workers only inside that child)."""
+    import os
+    import subprocess
+    import sys
+    cache_dir = cache_dir or os.environ.get("VORO_SCENE_CACHE", "/tmp/voro_scene_cache")
+    os.makedirs(cache_dir, exist_ok=True)
+    path = os.path.join(cache_dir, f"{name}.npz")
+    if not os.path.exists(path):
+        tmp = path + ".tmp.npz"
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        subprocess.run([sys.executable, "-m", "paper_2608_17682_amd.synth", name, tmp], check=True,
+                       cwd=root)
+        os.replace(tmp, path)
+    return load_scene(path)
+
+
+if __name__ == "__main__":
+    import sys
+    save_scene(_build_config(sys.argv[1]), sys.argv[2])
