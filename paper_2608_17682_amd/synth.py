@@ -547,27 +547,44 @@ def delaunay_csr_parallel(sites: np.ndarray, blocks_per_axis: int = 4, workers: 
 
 # ------------------------------------------------------------ scene cache
 
-def _build_config(name: str) -> Scene:
+def _build_config(name: str):
+    """(scene, camera extras) of a named workload."""
     if name == "config2":
-        return config2()[0]
+        return config2()[0], {}
     if name == "config3":
-        return config3(with_csr=True)[0]
+        scene, cams = config3(with_csr=True)
+        return scene, {"cam_c2w": cams[0].c2w}
     if name == "config5":
-        return config5()[0]
+        return config5()[0], {}
     if name.startswith("shell"):
-        return scene_shell(int(name[5:]), 8, seed=5)
+        return scene_shell(int(name[5:]), 8, seed=5), {}
     raise ValueError(name)
 
 
-def save_scene(scene: Scene, path: str):
+def save_scene(scene: Scene, path: str, extras=None):
     np.savez(path, sites=scene.sites, density=scene.density, texels=scene.texels,
-             nbr_off=scene.nbr_off, nbr_idx=scene.nbr_idx, name=np.array(scene.name))
+             nbr_off=scene.nbr_off, nbr_idx=scene.nbr_idx, name=np.array(scene.name),
+             **{f"x_{k}": v for k, v in (extras or {}).items()})
 
 
 def load_scene(path: str) -> Scene:
     z = np.load(path, allow_pickle=False)
-    return Scene(z["sites"], z["density"], z["texels"], z["nbr_off"], z["nbr_idx"],
-                 name=str(z["name"]))
+    s = Scene(z["sites"], z["density"], z["texels"], z["nbr_off"], z["nbr_idx"],
+              name=str(z["name"]))
+    s.extras = {k[2:]: z[k] for k in z.files if k.startswith("x_")}
+    return s
+
+
+def config3_camera(scene: Scene) -> Camera:
+    """The config-3 interior view of a cached config-3 scene."""
+    return Camera(PINHOLE, 1280, 840, np.asarray(scene.extras["cam_c2w"], np.float64),
+                  math.radians(60.0), 14.0)
+
+
+def scene_cache_path(name: str, cache_dir: str = None) -> str:
+    import os
+    cache_dir = cache_dir or os.environ.get("VORO_SCENE_CACHE", "/tmp/voro_scene_cache")
+    return os.path.join(cache_dir, f"{name}.npz")
 
 
 def scene_cached(name: str, cache_dir: str = None) -> Scene:
@@ -577,11 +594,10 @@ def scene_cached(name: str, cache_dir: str = None) -> Scene:
     import os
     import subprocess
     import sys
-    cache_dir = cache_dir or os.environ.get("VORO_SCENE_CACHE", "/tmp/voro_scene_cache")
-    os.makedirs(cache_dir, exist_ok=True)
-    path = os.path.join(cache_dir, f"{name}.npz")
+    path = scene_cache_path(name, cache_dir)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
     if not os.path.exists(path):
-        tmp = path + ".tmp.npz"
+        tmp = path[:-4] + ".tmp.npz"
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         subprocess.run([sys.executable, "-m", "paper_2608_17682_amd.synth", name, tmp], check=True,
                        cwd=root)
@@ -591,4 +607,5 @@ def scene_cached(name: str, cache_dir: str = None) -> Scene:
 
 if __name__ == "__main__":
     import sys
-    save_scene(_build_config(sys.argv[1]), sys.argv[2])
+    _scene, _extras = _build_config(sys.argv[1])
+    save_scene(_scene, sys.argv[2], _extras)

@@ -1,0 +1,220 @@
+"""GPU parity at the full scene sizes - 2M sites (one 1280x840 interior view,
+forward and adjoint) and 4M sites (8 mixed views in one persistent launch,
+binary16 texels) - on sampled rays the oracle evaluates one by one, in the
+launch configuration bench.py times (Morton-ordered cells, default launch
+parameters).  The oracle runs in a child process (oracle.batch)."""
+import os
+import subprocess
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cameras
+from paper_2608_17682_amd import synth, voro
+from helpers import f32
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1500)]
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def run_oracle(scene_path, rays):
+    td = tempfile.mkdtemp()
+    rp, op = os.path.join(td, "rays.npz"), os.path.join(td, "out.npz")
+    np.savez(rp, **rays)
+    subprocess.run([sys.executable, "-m", "oracle.batch", scene_path, rp, op], check=True, cwd=ROOT)
+    z = np.load(op, allow_pickle=False)
+    return {k: z[k] for k in z.files}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    voro.lib()
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def morton_scene(scene, dev, tex_dtype=None):
+    ds0 = voro.device_scene(scene, dev, tex_dtype=tex_dtype)
+    ds, perm, inv = voro.voro_morton_reorder(ds0)
+    del ds0
+    voro.voro_prepare(ds)
+    return ds, perm.cpu().numpy(), inv.cpu().numpy()
+
+
+def assert_grad_close(got, want, name):
+    scale = max(1e-12, float(np.abs(want).max()))
+    err = float(np.abs(got - want).max())
+    assert err <= 1e-4 * scale + 1e-6, (name, err, scale)
+
+
+class Case:
+    pass
+
+
+@pytest.fixture(scope="module")
+def c3(dev):
+    c = Case()
+    announce("config3: 2M-site scene (built by a child process on a cache miss)")
+    c.scene = synth.scene_cached("config3")
+    c.cam = synth.config3_camera(c.scene)
+    o, d, tm, _ = cameras.camera_rays_of(c.cam)
+    c.pick = synth.sample_pixels(c.cam.n_pixels, 24, 33)
+    c.o, c.d, c.tm = f32(o[c.pick]), f32(d[c.pick]), f32(tm[c.pick])
+    c.g_rgb = synth.upstream(len(c.pick), 3, with_gT=False)[0]
+    announce("config3: oracle on 24 sampled rays")
+    c.orc = run_oracle(synth.scene_cache_path("config3"),
+                       dict(o=c.o, d=c.d, tmax=c.tm, g_rgb=c.g_rgb,
+                            g_T=np.zeros(len(c.pick), np.float32),
+                            grad_skip_degenerate=np.array(True)))
+    c.ds, c.perm, c.inv = morton_scene(c.scene, dev)
+    return c
+
+
+def test_config3_forward_sampled_rays(dev, c3):
+    announce("config3: forward of the sampled rays")
+    O, D, TM = to_dev(c3.o, dev), to_dev(c3.d, dev), to_dev(c3.tm, dev)
+    S = voro.voro_locate_origins(c3.ds, O[:1]).expand(len(c3.o)).contiguous()
+    R = len(c3.o)
+    p = voro.default_params(max_record=128)
+    nsteps = torch.empty(R, dtype=torch.int32, device=dev)
+    cells = torch.empty((R, 128), dtype=torch.int32, device=dev)
+    rgb, T = voro.voro_render_fwd(c3.ds, O, D, TM, S, p, nsteps=nsteps, cells=cells)
+    rgb, T, K, cells = (x.cpu().numpy() for x in (rgb, T, nsteps, cells))
+    np.testing.assert_allclose(rgb, c3.orc["rgb"], atol=1e-4, rtol=0)
+    np.testing.assert_allclose(T, c3.orc["T"], atol=1e-4, rtol=0)
+    ok = ~c3.orc["degenerate"]
+    assert ok.mean() > 0.8
+    for r in np.nonzero(ok)[0]:
+        k = int(c3.orc["K"][r])
+        assert K[r] == k
+        kk = min(k, 128)
+        np.testing.assert_array_equal(c3.perm[cells[r, :kk]], c3.orc["cells"][r, :kk])
+    assert K.mean() > 20
+
+
+def test_config3_adjoint_sampled_rays(dev, c3):
+    ok = np.nonzero(~c3.orc["degenerate"])[0]
+    announce("config3: adjoint of the sampled rays")
+    O, D, TM = to_dev(c3.o, dev), to_dev(c3.d, dev), to_dev(c3.tm, dev)
+    S = voro.voro_locate_origins(c3.ds, O[:1]).expand(len(c3.o)).contiguous()
+    # the oracle's gradient sums cover the non-degenerate rays
+    sel = ok
+    orc = c3.orc
+    ts = torch.from_numpy(sel).to(dev)
+    rgb, T = voro.voro_render_fwd(c3.ds, O[ts], D[ts], TM[ts], S[ts])
+    gs, gd, gt = voro.voro_render_bwd(c3.ds, O[ts], D[ts], TM[ts], S[ts], rgb, T,
+                                      to_dev(c3.g_rgb[sel], dev))
+    gs, gd, gt = gs.cpu().numpy(), gd.cpu().numpy(), gt.cpu().numpy()
+    ids = orc["grad_cells"]
+    k = c3.inv[ids]                      # Morton index of each oracle cell
+    assert_grad_close(gs[k], orc["grad_sites"], "sites")
+    assert_grad_close(gd[k], orc["grad_density"], "density")
+    assert_grad_close(gt[k], orc["grad_texels"], "texels")
+    mask = np.ones(len(gd), bool)
+    mask[k] = False
+    assert np.all(gd[mask] == 0) and np.all(gs[mask] == 0) and np.all(gt[mask] == 0)
+
+
+def test_config3_full_frame_views_equals_explicit(dev, c3):
+    announce("config3: full 1280x840 frame, persistent launch vs explicit rays")
+    rgb_v, T_v, _ = voro.voro_render_views_fwd(c3.ds, [c3.cam])
+    O, D, TM = voro.voro_gen_rays([c3.cam], dev)
+    S = voro.voro_locate_origins(c3.ds, O[:1]).expand(O.shape[0]).contiguous()
+    rgb_e, T_e = voro.voro_render_fwd(c3.ds, O, D, TM, S, voro.default_params(img_w=1280))
+    assert torch.equal(rgb_v, rgb_e) and torch.equal(T_v, T_e)
+    # and the sampled pixels against the oracle (FP32 rays from the GPU differ
+    # from the oracle's by rounding only)
+    rgb_v = rgb_v.cpu().numpy()
+    ok = ~c3.orc["degenerate"]
+    np.testing.assert_allclose(rgb_v[c3.pick[ok]], c3.orc["rgb"][ok], atol=1e-4, rtol=0)
+
+
+@pytest.fixture(scope="module")
+def c5(dev):
+    c = Case()
+    announce("config5: 4M-site scene (built by a child process on a cache miss)")
+    c.scene = synth.scene_cached("config5")
+    c.cams = synth.config5_cameras(1.0)
+    rays = {"o": [], "d": [], "tmax": []}
+    c.samples = []  # (view, pixel, first oracle ray, spp)
+    n = 0
+    for v, cam in enumerate(c.cams):
+        o, d, tm, valid = cameras.camera_rays_of(cam)
+        cand = np.nonzero(valid.reshape(cam.n_pixels, cam.spp).all(1))[0]
+        pix = cand[synth.sample_pixels(len(cand), 2, 50 + v)]
+        for p in pix:
+            rs = slice(p * cam.spp, (p + 1) * cam.spp)
+            rays["o"].append(o[rs])
+            rays["d"].append(d[rs])
+            rays["tmax"].append(tm[rs])
+            c.samples.append((v, int(p), n, cam.spp))
+            n += cam.spp
+    rays = {k: f32(np.concatenate(v)) for k, v in rays.items()}
+    rays["texel_dtype"] = np.array("float16")
+    announce(f"config5: oracle on {n} sampled rays (binary16 texels)")
+    c.orc = run_oracle(synth.scene_cache_path("config5"), rays)
+    c.ds, c.perm, c.inv = morton_scene(c.scene, dev, tex_dtype="float16")
+    return c
+
+
+def test_config5_persistent_views_forward(dev, c5):
+    announce("config5: 8 views, one persistent forward launch")
+    p = voro.default_params()
+    rgb, T, ray_rgbT = voro.voro_render_views_fwd(c5.ds, c5.cams, p)
+    rgb, T = rgb.cpu().numpy(), T.cpu().numpy()
+    off = np.cumsum([0] + [cam.n_pixels for cam in c5.cams])
+    checked = 0
+    for v, pix, r0, spp in c5.samples:
+        if c5.orc["degenerate"][r0:r0 + spp].any():
+            continue
+        np.testing.assert_allclose(rgb[off[v] + pix], c5.orc["rgb"][r0:r0 + spp].mean(0),
+                                   atol=1e-4, rtol=0)
+        np.testing.assert_allclose(T[off[v] + pix], c5.orc["T"][r0:r0 + spp].mean(), atol=1e-4,
+                                   rtol=0)
+        checked += 1
+    assert checked >= 12
+    # fisheye pixels outside the image circle are empty
+    fe = 2
+    W = c5.cams[fe].width
+    assert T[off[fe]] == 1.0 and np.all(rgb[off[fe]] == 0)
+
+
+def test_config5_persistent_views_adjoint_equals_explicit(dev, c5):
+    announce("config5: persistent adjoint vs explicit-ray adjoint, all 7.7M rays")
+    p = voro.default_params()
+    npx = sum(cam.n_pixels for cam in c5.cams)
+    g_rgb = synth.upstream(npx, 5, with_gT=False)[0]
+    rgb, T, ray_rgbT = voro.voro_render_views_fwd(c5.ds, c5.cams, p)
+    gv = voro.voro_render_views_bwd(c5.ds, c5.cams, rgb, T, ray_rgbT, to_dev(g_rgb, dev), None, p)
+    O, D, TM = voro.voro_gen_rays(c5.cams, dev)
+    centres = to_dev(f32([cam.c2w[:, 3] for cam in c5.cams]), dev)
+    cc = voro.voro_locate_origins(c5.ds, centres)
+    nr = [cam.n_rays for cam in c5.cams]
+    hint = torch.cat([cc[i:i + 1].expand(k) for i, k in enumerate(nr)]).contiguous()
+    S = voro.voro_locate_origins(c5.ds, O, hint=hint)
+    rgb_e, T_e = voro.voro_render_fwd(c5.ds, O, D, TM, S, p)
+    # the persistent launch's per-ray results are the explicit path's, bit for bit
+    assert torch.equal(rgb_e, ray_rgbT[:, :3].contiguous()) and torch.equal(T_e, ray_rgbT[:, 3])
+    gr = []
+    off = 0
+    for cam in c5.cams:
+        gr.append(np.repeat(g_rgb[off:off + cam.n_pixels], cam.spp, 0) / cam.spp)
+        off += cam.n_pixels
+    ge = voro.voro_render_bwd(c5.ds, O, D, TM, S, rgb_e, T_e, to_dev(np.concatenate(gr), dev),
+                              None, p)
+    for a, b, name in zip(gv, ge, ("sites", "density", "texels")):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.isfinite(a).all()
+        assert np.abs(a - b).max() <= 1e-4 * max(1.0, np.abs(b).max()), name
