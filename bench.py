@@ -83,6 +83,96 @@ def oracle_sample(scene, cam, n_rays, workers, texels=None, seed=7):
     return pick, rgb, T, dt
 
 
+def bench_config3(scene, dev, args, timed):
+    """2M sites on 20 ellipsoid surfaces, one 1280x840 interior pinhole view;
+    forward + backward through the autograd Function (FP32), upstream dL/dRGB
+    ~ N(0,1).  Step = rays + centre cell + prepare + forward + backward."""
+    import torch
+    from paper_2608_17682_amd import synth, voro
+    from paper_2608_17682_amd.autograd import render
+    cam = synth.config3_camera(scene)
+    ds0 = voro.device_scene(scene, dev)
+    ds, perm, inv = voro.voro_morton_reorder(ds0)
+    del ds0
+    sites = ds.sites.clone().requires_grad_(True)
+    rho = torch.log(ds.density.clamp_min(1e-30)).requires_grad_(True)
+    tex = ds.texels.clone().requires_grad_(True)
+    g = torch.from_numpy(synth.upstream(cam.n_rays, 3, with_gT=False)[0]).to(dev)
+    ccam = [voro.camera_of(cam)]
+
+    def step():
+        O, D, TM = voro.voro_gen_rays(ccam, dev)
+        S = voro.voro_locate_origins(ds, O[:1]).expand(O.shape[0]).contiguous()
+        rgb, T = render(sites, torch.exp(rho), tex, ds.nbr_off, ds.nbr_idx, O, D, TM, S,
+                        voro.default_params(img_w=cam.width))
+        (rgb * g).sum().backward()
+
+    # instrumented forward for the step counts
+    st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    voro.voro_prepare(ds)
+    O, D, TM = voro.voro_gen_rays(ccam, dev)
+    S = voro.voro_locate_origins(ds, O[:1]).expand(O.shape[0]).contiguous()
+    voro.voro_render_fwd(ds, O, D, TM, S, voro.default_params(img_w=cam.width), stats=st)
+    stats = stats_dict(st)
+    steps = max(2, args.steps // 2)
+    s = timed(step, steps, 1)
+    fwd_s = timed(lambda: voro.voro_render_fwd(ds, O, D, TM, S, voro.default_params(img_w=cam.width)),
+                  steps, 1)
+    return {"workload": "ellipsoids2M: 1.8M sites on 20 ellipsoid surfaces (sigma 50) + 200k "
+                        "uniform [-4,4]^3 (sigma 0.01), 8x8 f32 texels, 1280x840 interior "
+                        "pinhole, tmax 14, fwd+bwd via torch.autograd.Function",
+            "fwd_bwd_mrays_s": round(cam.n_rays * steps / s / 1e6, 2),
+            "fwd_kernel_mrays_s": round(cam.n_rays * steps / fwd_s / 1e6, 2),
+            "ms_per_step": round(s * 1e3 / steps, 3),
+            "mean_cells_per_ray": round(stats["steps"] / max(1, stats["rays"]), 2)}
+
+
+def bench_config5(scene, dev, args, timed):
+    """4M sites (config-2 structure), binary16 texels, 8 views in one persistent
+    launch: 2 pinhole 1280x840, 2 fisheye 180 deg 1024x1024, 2 rolling shutter
+    960x540, 2 thin lens 640x480 x 4 samples.  Forward, and forward + backward."""
+    import torch
+    from paper_2608_17682_amd import synth, voro
+    cams = synth.config5_cameras(1.0)
+    ds0 = voro.device_scene(scene, dev, tex_dtype="float16")
+    ds, perm, inv = voro.voro_morton_reorder(ds0)
+    del ds0
+    voro.voro_prepare(ds)
+    ccams = [voro.camera_of(c) for c in cams]
+    nr, npx = voro.voro_camera_counts(ccams)
+    rgb = torch.empty((npx, 3), device=dev)
+    T = torch.empty(npx, device=dev)
+    ray = torch.empty((nr, 4), device=dev)
+    st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    voro.voro_render_views_fwd(ds, ccams, None, rgb, T, ray, stats=st)
+    stats = stats_dict(st)
+    rays = stats["rays"]   # fisheye pixels outside the image circle emit no ray
+
+    def fwd():
+        voro.voro_prepare(ds)
+        voro.voro_render_views_fwd(ds, ccams, None, rgb, T, ray)
+
+    g = torch.from_numpy(synth.upstream(npx, 5, with_gT=False)[0]).to(dev)
+    gs = torch.zeros((ds.n, 3), device=dev)
+    gd = torch.zeros(ds.n, device=dev)
+    gt = torch.zeros(tuple(ds.texels.shape), device=dev)
+
+    def fwdbwd():
+        fwd()
+        voro.voro_render_views_bwd(ds, ccams, rgb, T, ray, g, None, None, gs, gd, gt)
+
+    steps = max(2, args.steps // 2)
+    sf = timed(fwd, steps, 1)
+    sb = timed(fwdbwd, steps, 1)
+    return {"workload": "shell4M: 2.8M shell + 1.2M uniform sites, 8x8 f16 texels, 8 mixed views "
+                        "(2 pinhole 1280x840, 2 fisheye 1024^2, 2 rolling shutter 960x540, "
+                        "2 thin lens 640x480x4) in one persistent launch",
+            "rays": rays, "fwd_mrays_s": round(rays * steps / sf / 1e6, 2),
+            "fwd_bwd_mrays_s": round(rays * steps / sb / 1e6, 2),
+            "fwd_ms": round(sf * 1e3 / steps, 3), "fwd_bwd_ms": round(sb * 1e3 / steps, 3),
+            "mean_cells_per_ray": round(stats["steps"] / max(1, rays), 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +182,8 @@ def main():
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--no-morton", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip half texels and fwd+bwd")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2M-site (fwd+bwd) and 4M-site (8 views) workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-rays", type=int, default=192)
     ap.add_argument("--copy-probe", action="store_true",
@@ -130,6 +222,18 @@ def main():
         workers = min(16, os.cpu_count() or 1)
         oracle_leg = (workers,) + oracle_sample(scene, cams[0], args.oracle_rays, workers)
         log(f"oracle leg: {len(oracle_leg[1])} rays in {oracle_leg[4]:.1f}s on {workers} processes")
+
+    # the 2M/4M-site scenes: adjacency built in a child process (cached)
+    large = {}
+    if not args.no_large and not args.no_extras:
+        for name in ("config3", "config5"):
+            t0 = time.perf_counter()
+            try:
+                large[name] = synth.scene_cached(name)
+                log(f"{name}: {large[name].n} sites ready in {time.perf_counter() - t0:.1f}s")
+            except Exception as e:  # a large workload must never cost the headline
+                large[name] = e
+                log(f"{name}: scene failed: {e!r}")
 
     dev = torch.device("cuda:0")
     ds0 = voro.device_scene(scene, dev)
@@ -232,7 +336,20 @@ def main():
                                            gs, gd, gt)
         s = timed(fb, max(2, args.steps // 2), 1)
         extras["fwd_bwd_f32_mrays_s"] = round(rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
+        del gs, gd, gt
         log(f"extras: {extras}")
+        for name, fn in (("config3", bench_config3), ("config5", bench_config5)):
+            if name not in large:
+                continue
+            try:
+                if isinstance(large[name], Exception):
+                    raise large[name]
+                extras[name] = fn(large[name], dev, args, timed)
+            except Exception as e:
+                extras[name] = {"error": repr(e)}
+            log(f"{name}: {extras[name]}")
+            large[name] = None
+            torch.cuda.empty_cache()
 
     cpu_baseline = None
     if oracle_leg is not None:

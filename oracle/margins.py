@@ -10,8 +10,11 @@ from __future__ import annotations
 
 import math
 
-EPS_SEQ = 1e-5      # FP64 gap (relative to max(1,|t|)) below which a step is a near tie
-EPS_DELTA = 1e-5    # segments shorter than this are near-degenerate crossings
+# The GPU re-decides exits whose FP32 gap is within 1e-6 max(1,|t|) in FP64;
+# FP32 crossing errors are ~1e-7 per unit t, so an FP64 gap of 4x the window
+# is decided identically by both sides.
+EPS_SEQ = 4e-6      # FP64 gap (relative to max(1,|t|)) below which a step is a near tie
+EPS_DELTA = 1e-7    # segments shorter than this are crossings next to a cell edge
 EPS_TMAX = 1e-5     # exits this close to tmax may end the ray one step earlier or later
 EPS_TSTOP = 1e-4    # relative margin of T_k to t_stop (FP32 T carries ~K*1e-7)
 
