@@ -7,7 +7,8 @@ read).  RAYS.npz holds o [R,3], d [R,3], tmax [R] (float32) and optionally
 g_rgb [R,3], g_T [R] (upstream gradients), start [R], t_stop, skip_w,
 texel_dtype = "float16" (texels rounded to binary16 before use) and
 grad_skip_degenerate (sum gradients over the non-degenerate rays only).  Writes rgb [R,3],
-T [R], K [R], cells [R,128] (-1 padded), degenerate [R] (oracle.margins), and
+T [R], K [R], cells [R,128] (-1 padded), degenerate [R] and stop_degenerate [R]
+(oracle.margins), and
 with upstream gradients the FP64 gradients restricted to the touched cells:
 grad_cells [C], grad_sites [C,3], grad_density [C], grad_texels [C,R,R,4].
 
@@ -38,6 +39,7 @@ def _job(args):
         rec = render.render_ray(sites, density, texels, o[r], d[r], float(tm[r]),
                                 start=None if st is None else int(st[r]), **kw)
         deg = margins.degenerate(rec, kw.get("t_stop", 1e-4), float(tm[r]))
+        sdeg = margins.stop_degenerate(rec, kw.get("t_stop", 1e-4))
         grad = None
         if gr is not None and not (skip_degenerate and deg):
             g_sites = _Sparse3()
@@ -46,7 +48,7 @@ def _job(args):
             adjoint.grad_ray(sites, density, texels, o[r], d[r], float(tm[r]), rec, gr[r], gt[r],
                              g_sites, g_den, g_tex)
             grad = (g_sites.d, g_den.d, g_tex.d)
-        out.append((rec.rgb, rec.T, rec.K, rec.cells[:128], deg, grad))
+        out.append((rec.rgb, rec.T, rec.K, rec.cells[:128], deg, grad, sdeg))
     return out
 
 
@@ -121,7 +123,8 @@ def main(argv):
     with ctx.Pool(workers, initializer=_init, initargs=(sites, density, texels, kw)) as pool:
         res = [x for part in pool.map(_job, jobs) for x in part]
     out = {"rgb": np.array([x[0] for x in res]), "T": np.array([x[1] for x in res]),
-           "K": np.array([x[2] for x in res]), "degenerate": np.array([x[4] for x in res])}
+           "K": np.array([x[2] for x in res]), "degenerate": np.array([x[4] for x in res]),
+           "stop_degenerate": np.array([x[6] for x in res])}
     cells = np.full((R, 128), -1, np.int64)
     for r, x in enumerate(res):
         cells[r, :len(x[3])] = x[3]

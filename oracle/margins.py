@@ -10,16 +10,32 @@ from __future__ import annotations
 
 import math
 
-# The GPU re-decides exits whose FP32 gap is within 1e-6 max(1,|t|) in FP64;
-# FP32 crossing errors are ~1e-7 per unit t, so an FP64 gap of 4x the window
-# is decided identically by both sides.
-EPS_SEQ = 4e-6      # FP64 gap (relative to max(1,|t|)) below which a step is a near tie
+# The GPU re-decides exits whose FP32 gap is within W = 1e-6 max(1,|t|) in
+# FP64.  With FP32 crossing errors E ~ 1e-7 per unit t (up to ~1e-6 for
+# grazing faces), every decision whose true gap exceeds E comes out the same,
+# and so does every one whose FP32 gap falls inside W; a margin of 2W covers
+# the remaining grazing cases.
+EPS_SEQ = 2e-6      # FP64 gap (relative to max(1,|t|)) below which a step is a near tie
 EPS_DELTA = 1e-7    # segments shorter than this are crossings next to a cell edge
 EPS_TMAX = 1e-5     # exits this close to tmax may end the ray one step earlier or later
 EPS_TSTOP = 1e-4    # relative margin of T_k to t_stop (FP32 T carries ~K*1e-7)
 
 
+def stop_degenerate(rec, t_stop=1e-4) -> bool:
+    """T lands next to t_stop: FP32 may stop one segment earlier or later, which
+    changes the colour by up to t_stop (all other degeneracies change it by the
+    length of a near-zero segment only)."""
+    if rec is None or t_stop <= 0:
+        return False
+    for k in range(rec.K):
+        Tk = rec.T_before[k + 1] if k + 1 < rec.K else rec.T
+        if abs(Tk - t_stop) < EPS_TSTOP * t_stop:
+            return True
+    return False
+
+
 def degenerate(rec, t_stop=1e-4, tmax=None) -> bool:
+    """Any step whose decision FP32 may take differently (sequence comparison)."""
     if rec is None:
         return False
     if rec.start_gap < 1e-9:
@@ -32,7 +48,4 @@ def degenerate(rec, t_stop=1e-4, tmax=None) -> bool:
             return True
         if tmax is not None and math.isfinite(t) and abs(t - tmax) < EPS_TMAX:
             return True
-        Tk = rec.T_before[k + 1] if k + 1 < rec.K else rec.T
-        if t_stop > 0 and abs(Tk - t_stop) < EPS_TSTOP * t_stop:
-            return True
-    return False
+    return stop_degenerate(rec, t_stop)

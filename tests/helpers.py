@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle.margins import degenerate  # noqa: F401
+from oracle.margins import degenerate, stop_degenerate  # noqa: F401
 
 
 def f32(a):

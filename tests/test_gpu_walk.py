@@ -13,7 +13,7 @@ import torch
 
 from oracle import adjoint, cameras, render, walk
 from paper_2608_17682_amd import synth, voro
-from helpers import degenerate, f32
+from helpers import degenerate, f32, stop_degenerate
 
 pytestmark = pytest.mark.gpu
 
@@ -304,7 +304,7 @@ def test_views_match_oracle_sampled(dev, c1):
             rgb_o, T_o, recs = render.render_rays(c1.scene.sites, c1.scene.density,
                                                   c1.scene.texels, f32(o[rs]), f32(d[rs]),
                                                   f32(tm[rs]))
-            if any(degenerate(r, 1e-4, 4.0) for r in recs):
+            if any(stop_degenerate(r, 1e-4) for r in recs):
                 continue
             np.testing.assert_allclose(rgb_v[off + p], rgb_o.mean(0), atol=1e-4, rtol=0)
             np.testing.assert_allclose(T_v[off + p], T_o.mean(), atol=1e-4, rtol=0)
