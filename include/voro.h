@@ -131,7 +131,7 @@ typedef struct voro_scene {
  *               images of this width and waves take screen tiles; 0 = rays
  *               are walked in index order                               [0]
  *   max_record  cells recorded per ray in voro_render_fwd's `cells`     [0]
- *   block       threads per workgroup: 64, 128, 256, 512 (0 = 256)       [0]
+ *   block       threads per workgroup: 64, 128 or 256 (0 = 256)          [0]
  */
 typedef struct voro_params {
   float t_stop;

@@ -210,7 +210,10 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   __shared__ int s_keys[kTableCap];
   __shared__ float s_vals[16 * kTableCap];
   __shared__ int s_unit;
+  __shared__ int s_okeys[4][kOutbox];
+  __shared__ float s_ovals[4][16 * kOutbox];
   const GradTable tab{s_keys, s_vals};
+  const Outbox ob{s_okeys[wave], s_ovals[wave]};
   table_clear(tab);
   Counters cnt;
   int probe = 0;
@@ -248,7 +251,7 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
       u.gT = a.g_T ? a.g_T[p] * share : 0.0f;
     }
     // the whole wave walks its tile together (gradient records merge across lanes)
-    walk_backward<LPR, TEX>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, cnt);
+    walk_backward<LPR, TEX>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, ob, cnt);
     __syncthreads();
     table_flush(tab, a.g, RR, a.s.res);
     __syncthreads();

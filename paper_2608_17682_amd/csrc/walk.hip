@@ -156,12 +156,15 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
   }
   __shared__ int s_keys[kTableCap];
   __shared__ float s_vals[16 * kTableCap];
+  __shared__ int s_okeys[4][kOutbox];
+  __shared__ float s_ovals[4][16 * kOutbox];
   const GradTable tab{s_keys, s_vals};
+  const Outbox ob{s_okeys[wave], s_ovals[wave]};
   table_clear(tab);
   __syncthreads();
   // all lanes take part: the gradient records are merged across the wave,
   // then across the workgroup in the LDS table
-  walk_backward<LPR, TEX>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, cnt);
+  walk_backward<LPR, TEX>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, ob, cnt);
   __syncthreads();
   table_flush(tab, a.g, a.s.res * a.s.res, a.s.res);
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
