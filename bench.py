@@ -148,9 +148,12 @@ def bench_config5(scene, dev, args, timed):
     stats = stats_dict(st)
     rays = stats["rays"]   # fisheye pixels outside the image circle emit no ray
 
+    from paper_2608_17682_amd import autotune
+    pf, pb = autotune.params_for("config5", "fwd"), autotune.params_for("config5", "bwd")
+
     def fwd():
         voro.voro_prepare(ds)
-        voro.voro_render_views_fwd(ds, ccams, None, rgb, T, ray)
+        voro.voro_render_views_fwd(ds, ccams, pf, rgb, T, ray)
 
     g = torch.from_numpy(synth.upstream(npx, 5, with_gT=False)[0]).to(dev)
     gs = torch.zeros((ds.n, 3), device=dev)
@@ -159,7 +162,7 @@ def bench_config5(scene, dev, args, timed):
 
     def fwdbwd():
         fwd()
-        voro.voro_render_views_bwd(ds, ccams, rgb, T, ray, g, None, None, gs, gd, gt)
+        voro.voro_render_views_bwd(ds, ccams, rgb, T, ray, g, None, pb, gs, gd, gt)
 
     steps = max(2, args.steps // 2)
     sf = timed(fwd, steps, 1)
@@ -242,10 +245,15 @@ def main():
     else:
         ds, perm, inv = voro.voro_morton_reorder(ds0)
     voro.voro_prepare(ds)
-    params = voro.default_params(lanes_per_ray=args.lanes_per_ray)
-    if args.tile:
-        tw, th = (int(x) for x in args.tile.split("x"))
-        params.tile_w, params.tile_h = tw, th
+    from paper_2608_17682_amd import autotune
+    params = autotune.params_for("shell100k", "fwd")
+    params_bwd = autotune.params_for("shell100k", "bwd")
+    if args.lanes_per_ray or args.tile:
+        params = voro.default_params(lanes_per_ray=args.lanes_per_ray)
+        if args.tile:
+            tw, th = (int(x) for x in args.tile.split("x"))
+            params.tile_w, params.tile_h = tw, th
+        params_bwd = params
     ccams = [voro.camera_of(c) for c in cams]
     rays_per_frame = cams[0].n_rays
     rays_per_step = rays_per_frame * N_POSES
@@ -332,7 +340,7 @@ def main():
             voro.voro_prepare(ds)
             for i in range(N_POSES):
                 frame(i, params, ds)
-                voro.voro_render_views_bwd(ds, [ccams[i]], rgb, T, None, g_rgb, None, params,
+                voro.voro_render_views_bwd(ds, [ccams[i]], rgb, T, None, g_rgb, None, params_bwd,
                                            gs, gd, gt)
         s = timed(fb, max(2, args.steps // 2), 1)
         extras["fwd_bwd_f32_mrays_s"] = round(rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
@@ -399,7 +407,11 @@ def main():
                                "60deg, 8 orbit poses (r=3) per step, tmax 8, forward",
                    "rays_per_step": rays_per_step, "sites": scene.n,
                    "morton": not args.no_morton,
-                   "lanes_per_ray": args.lanes_per_ray, "tile": args.tile or "default"},
+                   "launch_fwd": {"lanes_per_ray": params.lanes_per_ray or 1,
+                                  "tile": f"{params.tile_w or 8}x{params.tile_h or 8}",
+                                  "block": params.block or 256},
+                   "launch_source": "autotune table" if autotune.lookup("shell100k", "fwd")
+                   and not (args.lanes_per_ray or args.tile) else "flags/defaults"},
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,
         "extras": extras,
