@@ -111,6 +111,13 @@ template <int LPR>
 __device__ __forceinline__ Top2 exit_search(const float4* __restrict__ edges, int off, int deg,
                                             int sub, float qx, float qy, float qz, float dx,
                                             float dy, float dz) {
+  // Per neighbour: with n = p_j - p_i, a = n.(n - 2q) = 2(|n|^2/2 - n.q) and
+  // b = n.w, the crossing is t_in + a / (2b); the search compares u = a / b
+  // (twice the offset from t_in) and halves the winners.  Faces behind the
+  // ray (b <= 0) get u = +inf.  Inside a lane the best two are kept by value
+  // (an exact tie always falls inside the FP64 re-decision window); lanes
+  // sharing a ray merge lexicographically in (t, id).
+  const float q2x = 2.0f * qx, q2y = 2.0f * qy, q2z = 2.0f * qz;
   Top2 r;
   r.t1 = kInf;
   r.j1 = -1;
@@ -121,12 +128,15 @@ __device__ __forceinline__ Top2 exit_search(const float4* __restrict__ edges, in
   for (int k = sub; k < deg; k += LPR) {
     const float4 E = e[k];
     const float b = dot3(E.x, E.y, E.z, dx, dy, dz);
-    if (b > 0.0f) {
-      const float h = 0.5f * dot3(E.x, E.y, E.z, E.x, E.y, E.z);
-      const float nq = dot3(E.x, E.y, E.z, qx, qy, qz);
-      const float t = (h - nq) * __builtin_amdgcn_rcpf(b);
-      top2_insert(r, t, __float_as_int(E.w));
-    }
+    const float a = dot3(E.x, E.y, E.z, E.x - q2x, E.y - q2y, E.z - q2z);
+    const float u = b > 0.0f ? a * __builtin_amdgcn_rcpf(b) : kInf;
+    const int j = __float_as_int(E.w);
+    const bool l1 = u < r.t1;
+    const bool l2 = u < r.t2;
+    r.t2 = l1 ? r.t1 : (l2 ? u : r.t2);
+    r.j2 = l1 ? r.j1 : (l2 ? j : r.j2);
+    r.t1 = l1 ? u : r.t1;
+    r.j1 = l1 ? j : r.j1;
   }
   if constexpr (LPR > 1) {
 #pragma unroll
@@ -138,6 +148,8 @@ __device__ __forceinline__ Top2 exit_search(const float4* __restrict__ edges, in
       top2_merge(r, u1, k1, u2, k2);
     }
   }
+  r.t1 *= 0.5f;
+  r.t2 *= 0.5f;
   return r;
 }
 
