@@ -132,6 +132,9 @@ typedef struct voro_scene {
  *               are walked in index order                               [0]
  *   max_record  cells recorded per ray in voro_render_fwd's `cells`     [0]
  *   block       threads per workgroup: 64, 128 or 256 (0 = 256)          [0]
+ *   schedule    multi-view launches: VORO_SCHEDULE_GRID (one work tile per
+ *               wave, hardware dispatch) or VORO_SCHEDULE_PERSISTENT (waves
+ *               loop over an XCD-partitioned tile queue); 0 = grid      [0]
  */
 typedef struct voro_params {
   float t_stop;
@@ -145,8 +148,11 @@ typedef struct voro_params {
   int32_t img_w;
   int32_t max_record;
   int32_t block;
-  int32_t reserved[5]; /* must be 0 */
+  int32_t schedule;
+  int32_t reserved[4]; /* must be 0 */
 } voro_params;
+
+enum { VORO_SCHEDULE_DEFAULT = 0, VORO_SCHEDULE_GRID = 1, VORO_SCHEDULE_PERSISTENT = 2 };
 
 /*
  * A camera (Sec. 6.5 / App. D: only ray generation changes).  c2w is the
@@ -282,11 +288,12 @@ voro_status voro_gen_rays(const voro_camera* cams, int32_t V, float* o, float* d
                           float* tmax, void* stream);
 
 /*
- * Persistent forward render of V views in one launch: rays are generated in
- * the kernel, waves take screen tiles of any view from a shared queue, the
- * start cell of each ray is the cell of its camera centre (found by a
- * brute-force search inside this call) or, for rolling-shutter rows and
- * thin-lens samples, reached from it by the nearest-site walk.
+ * Forward render of V views in one launch: rays are generated in the
+ * kernel, waves take screen tiles of any view (params.schedule: from the grid
+ * or from a persistent XCD-partitioned queue), the start cell of each ray is
+ * the cell of its camera centre (found by a brute-force search inside this
+ * call) or, for rolling-shutter rows and thin-lens samples, reached from it
+ * by the nearest-site walk.
  *   rgb [n_pixels,3], T [n_pixels] float out: per pixel (thin lens: the mean
  *   over its spp samples).
  *   ray_rgbT [n_rays,4] float out: per-ray (rgb, T); required when a view
@@ -301,7 +308,8 @@ voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_b
                                   uint64_t* stats, void* stream);
 
 /*
- * Adjoint of voro_render_views_fwd (persistent launch).  rgb/T (and ray_rgbT
+ * Adjoint of voro_render_views_fwd (one launch; workgroups walk workgroup
+ * tiles and merge gradient records in LDS before the atomics).  rgb/T (and ray_rgbT
  * when a view has spp > 1) are the saved forward outputs; g_rgb [n_pixels,3]
  * and g_T [n_pixels] (or NULL) the upstream gradients; a thin-lens pixel's
  * gradient is shared equally by its samples.  Accumulates (+=) like

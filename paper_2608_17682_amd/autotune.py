@@ -1,9 +1,10 @@
 """Launch-shape autotuner for the walk kernels.
 
-Picks, per workload and direction (forward / forward+adjoint), the number of
-lanes that share a ray's neighbour tests (rays per wave = 64 / lanes), the
-screen tile a wave walks, and the workgroup size, by timing the persistent
-multi-view launch with HIP events on the caller's device.  Results live in
+Picks, per workload and direction (forward / adjoint), the number of lanes
+that share a ray's neighbour tests (rays per wave = 64 / lanes), the screen
+tile a wave walks, the workgroup size and the schedule (grid or persistent
+queue), by timing the multi-view launch with HIP events on the caller's
+device.  Results live in
 ``autotune_table.json`` next to this file; ``lookup`` returns the tuned
 ``voro_params`` fields (or None).
 
@@ -21,7 +22,8 @@ TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table
 
 
 def candidates() -> List[dict]:
-    """Lanes per ray x wave tile (tile_w * tile_h * lanes = 64, aspect <= 8) x workgroup."""
+    """Lanes per ray x wave tile (tile_w * tile_h * lanes = 64, aspect <= 8) x workgroup
+    x schedule (1 = grid, 2 = persistent queue)."""
     out = []
     for lpr in (1, 2, 4, 8, 16):
         rays = 64 // lpr
@@ -30,7 +32,9 @@ def candidates() -> List[dict]:
             h = rays // w
             if max(w, h) <= 8 * min(w, h):
                 for block in (128, 256):
-                    out.append({"lanes_per_ray": lpr, "tile_w": w, "tile_h": h, "block": block})
+                    for schedule in (1, 2):
+                        out.append({"lanes_per_ray": lpr, "tile_w": w, "tile_h": h,
+                                    "block": block, "schedule": schedule})
             w *= 2
     return out
 
@@ -47,7 +51,7 @@ def lookup(workload: str, direction: str) -> Optional[dict]:
     e = _load().get(f"{workload}|{direction}")
     if not e:
         return None
-    return {k: e[k] for k in ("lanes_per_ray", "tile_w", "tile_h", "block")}
+    return {k: e[k] for k in ("lanes_per_ray", "tile_w", "tile_h", "block", "schedule") if k in e}
 
 
 def params_for(workload: str, direction: str):
@@ -108,7 +112,7 @@ def tune(ds, cams, reps: int = 3, cands: Iterable[dict] = None, log=print) -> Di
         res.sort(key=lambda x: x[0])
         ms, c = res[0]
         default_ms = next(m for m, cc in res if cc["lanes_per_ray"] == 1 and cc["tile_w"] == 8
-                          and cc["block"] == 256)
+                          and cc["block"] == 256 and cc["schedule"] == 1)
         best[direction] = dict(c, ms=round(ms, 4), default_ms=round(default_ms, 4),
                                rays=int(nr), candidates=len(res))
         log(f"[autotune] {direction}: best {c} {ms:.3f} ms (default 1x8x8/256: {default_ms:.3f} ms)")

@@ -94,7 +94,9 @@ voro_status check_params(const voro_params* p, bool backward) {
   if (p->max_record < 0) return fail(VORO_EINVAL, "max_record must be >= 0");
   if (!(p->block == 0 || p->block == 64 || p->block == 128 || p->block == 256))
     return fail(VORO_EINVAL, "block must be 0, 64, 128 or 256");
-  for (int i = 0; i < 5; ++i)
+  if (p->schedule < VORO_SCHEDULE_DEFAULT || p->schedule > VORO_SCHEDULE_PERSISTENT)
+    return fail(VORO_EINVAL, "unknown schedule %d", p->schedule);
+  for (int i = 0; i < 4; ++i)
     if (p->reserved[i] != 0) return fail(VORO_EINVAL, "params.reserved must be 0");
   return VORO_OK;
 }

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) k_gen_rays(CamTable ct, float* __restrict
   tmax[i] = tm;
 }
 
-// ---------------------------------------------------- persistent launch
+// ------------------------------------------------------ multi-view launch
 //
 // Work unit: one wave-sized screen tile (tile_w x tile_h rays) of one view.
 // A thin-lens view's samples form a (W g) x (H g) ray grid so a tile holds
@@ -120,7 +120,8 @@ struct TileRay {
 __device__ __forceinline__ bool tile_ray(const CamTable& ct, int unit, int sx, int sy, int grp,
                                          int tile_w, int tile_h, int unit_w, int unit_h,
                                          TileRay& tr) {
-  const int v = find_view(ct.tile_off, ct.V, unit);
+  // the unit is wave-uniform: keep the camera in scalar registers
+  const int v = __builtin_amdgcn_readfirstlane(find_view(ct.tile_off, ct.V, unit));
   const voro_camera& c = ct.cam[v];
   const int g = ct.g[v];
   const int gw = c.width * g;
@@ -151,18 +152,27 @@ __device__ __forceinline__ RayIn views_ray(const ViewsArgs& a, const TileRay& tr
   return r;
 }
 
-template <int LPR, int TEX>
+// PERSIST: waves loop over the XCD-partitioned tile queue; otherwise each
+// wave of the grid takes one tile (workgroups renumbered per XCD) and the
+// hardware dispatcher balances the load.
+template <int LPR, int TEX, bool PERSIST>
 __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int grp = lane / LPR;
   const int sub = lane % LPR;
   const int xcd = blockIdx.x % kXcd;
   Counters cnt;
   uint32_t capped_n = 0;
   int probe = 0;
+  int tile = PERSIST ? -1 : xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
   for (;;) {
-    const int tile = next_tile(a.counters, a.total_tiles, xcd, lane, probe);
-    if (tile < 0) break;
+    if constexpr (PERSIST) {
+      tile = next_tile(a.counters, a.total_tiles, xcd, lane, probe);
+      if (tile < 0) break;
+    } else if (tile >= a.total_tiles) {
+      break;
+    }
     TileRay tr;
     if (tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr)) {
       bool capped = false;
@@ -184,6 +194,7 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
         if (a.nsteps) a.nsteps[tr.ray] = out.k;
       }
     }
+    if constexpr (!PERSIST) break;
   }
   if (a.stats) {
     flush_counters(cnt, sub == 0, lane, a.stats);
@@ -195,7 +206,7 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
 // Backward work unit: a workgroup tile (the waves' tiles side by side, 2
 // wide), walked by the whole workgroup into one LDS gradient table that is
 // flushed to global memory before the next unit.
-template <int LPR, int TEX>
+template <int LPR, int TEX, bool PERSIST>
 __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -217,11 +228,17 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   table_clear(tab);
   Counters cnt;
   int probe = 0;
+  int unit = PERSIST ? -1 : xcd_block(blockIdx.x, gridDim.x);
   for (;;) {
-    if (threadIdx.x == 0) s_unit = next_unit(a.counters, a.total_tiles, xcd, probe);
-    __syncthreads();
-    const int unit = s_unit;
-    if (unit < 0) break;
+    if constexpr (PERSIST) {
+      if (threadIdx.x == 0) s_unit = next_unit(a.counters, a.total_tiles, xcd, probe);
+      __syncthreads();
+      unit = s_unit;
+      if (unit < 0) break;
+    } else {
+      __syncthreads();
+      if (unit >= a.total_tiles) break;
+    }
     TileRay tr;
     const bool has = tile_ray(a.ct, unit, wave % wx, wave / wx, grp, a.tile_w, a.tile_h, unit_w,
                               unit_h, tr);
@@ -255,6 +272,7 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
     __syncthreads();
     table_flush(tab, a.g, RR, a.s.res);
     __syncthreads();
+    if constexpr (!PERSIST) break;
   }
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
 }
@@ -313,16 +331,16 @@ static CamTable make_table(const voro_camera* cams, int V, int tile_w, int tile_
 
 template <int LPR, int TEX>
 static int persistent_blocks(bool backward, int block) {
-  static int cached[2][5] = {};
-  int& c = cached[backward ? 1 : 0][block / 128];
+  static int cached[2][3] = {};
+  int& c = cached[backward ? 1 : 0][block == 64 ? 0 : (block == 128 ? 1 : 2)];
   if (c) return c;
   int dev = 0, cus = 0, occ = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (backward)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX>, block, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX, true>, block, 0);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX>, block, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, true>, block, 0);
   (void)hipGetLastError();
   c = max(kXcd, max(1, cus) * max(1, occ));
   c = (c / kXcd) * kXcd;
@@ -330,23 +348,33 @@ static int persistent_blocks(bool backward, int block) {
 }
 
 template <int LPR, int TEX>
-static void launch_views_t(bool backward, const ViewsArgs& a, int block, hipStream_t st) {
-  const int blocks = persistent_blocks<LPR, TEX>(backward, block);
-  if (backward)
-    hipLaunchKernelGGL((k_views_bwd<LPR, TEX>), dim3(blocks), dim3(block), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_views_fwd<LPR, TEX>), dim3(blocks), dim3(block), 0, st, a);
+static void launch_views_t(bool backward, bool persist, const ViewsArgs& a, int block,
+                           hipStream_t st) {
+  const int nwaves = block / 64;
+  if (persist) {
+    const int blocks = persistent_blocks<LPR, TEX>(backward, block);
+    if (backward)
+      hipLaunchKernelGGL((k_views_bwd<LPR, TEX, true>), dim3(blocks), dim3(block), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, true>), dim3(blocks), dim3(block), 0, st, a);
+  } else if (backward) {
+    hipLaunchKernelGGL((k_views_bwd<LPR, TEX, false>), dim3(max(1, a.total_tiles)), dim3(block),
+                       0, st, a);
+  } else {
+    const int blocks = max(1, (a.total_tiles + nwaves - 1) / nwaves);
+    hipLaunchKernelGGL((k_views_fwd<LPR, TEX, false>), dim3(blocks), dim3(block), 0, st, a);
+  }
 }
 
 template <int TEX>
-static void launch_views_lpr(int lpr, bool backward, const ViewsArgs& a, int block,
+static void launch_views_lpr(int lpr, bool backward, bool persist, const ViewsArgs& a, int block,
                              hipStream_t st) {
   switch (lpr) {
-    case 1: launch_views_t<1, TEX>(backward, a, block, st); break;
-    case 2: launch_views_t<2, TEX>(backward, a, block, st); break;
-    case 4: launch_views_t<4, TEX>(backward, a, block, st); break;
-    case 8: launch_views_t<8, TEX>(backward, a, block, st); break;
-    default: launch_views_t<16, TEX>(backward, a, block, st); break;
+    case 1: launch_views_t<1, TEX>(backward, persist, a, block, st); break;
+    case 2: launch_views_t<2, TEX>(backward, persist, a, block, st); break;
+    case 4: launch_views_t<4, TEX>(backward, persist, a, block, st); break;
+    case 8: launch_views_t<8, TEX>(backward, persist, a, block, st); break;
+    default: launch_views_t<16, TEX>(backward, persist, a, block, st); break;
   }
 }
 
@@ -392,10 +420,11 @@ static voro_status views_common(bool backward, const voro_scene* scene, void* ws
   if ((st = check_launch("views: setup")) != VORO_OK) return st;
   if ((st = launch_locate_brute(scene, ws, origins, V, centers, s)) != VORO_OK) return st;
   const int block = L.block;
+  const bool persist = params->schedule == VORO_SCHEDULE_PERSISTENT;
   switch (scene->tex_dtype) {
-    case VORO_TEX_F32: launch_views_lpr<VORO_TEX_F32>(L.lpr, backward, a, block, s); break;
-    case VORO_TEX_F16: launch_views_lpr<VORO_TEX_F16>(L.lpr, backward, a, block, s); break;
-    default: launch_views_lpr<VORO_TEX_BF16>(L.lpr, backward, a, block, s); break;
+    case VORO_TEX_F32: launch_views_lpr<VORO_TEX_F32>(L.lpr, backward, persist, a, block, s); break;
+    case VORO_TEX_F16: launch_views_lpr<VORO_TEX_F16>(L.lpr, backward, persist, a, block, s); break;
+    default: launch_views_lpr<VORO_TEX_BF16>(L.lpr, backward, persist, a, block, s); break;
   }
   return check_launch(backward ? "voro_render_views_bwd" : "voro_render_views_fwd");
 }

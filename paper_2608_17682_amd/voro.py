@@ -28,6 +28,7 @@ VORO_EWORKSPACE = -5
 
 TEX_F32, TEX_F16, TEX_BF16 = 0, 1, 2
 CAM_PINHOLE, CAM_FISHEYE, CAM_ROLLING_SHUTTER, CAM_THIN_LENS = 0, 1, 2, 3
+SCHEDULE_DEFAULT, SCHEDULE_GRID, SCHEDULE_PERSISTENT = 0, 1, 2
 MAX_VIEWS = 16
 
 STAT_NAMES = ["rays", "steps", "degree_sum", "max_steps", "nan", "bad_start", "fp64_redecide",
@@ -63,7 +64,8 @@ class voro_params(ctypes.Structure):
                 ("appearance", ctypes.c_int32), ("lanes_per_ray", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("img_w", ctypes.c_int32), ("max_record", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("block", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class voro_camera(ctypes.Structure):
