@@ -128,8 +128,7 @@ def bench_config3(scene, dev, args, timed):
 
 
 def bench_config5(scene, dev, args, timed):
-    """4M sites (config-2 structure), binary16 texels, 8 views in one persistent
-    launch: 2 pinhole 1280x840, 2 fisheye 180 deg 1024x1024, 2 rolling shutter
+    """4M sites (config-2 structure), binary16 texels, 8 views in one launch: 2 pinhole 1280x840, 2 fisheye 180 deg 1024x1024, 2 rolling shutter
     960x540, 2 thin lens 640x480 x 4 samples.  Forward, and forward + backward."""
     import torch
     from paper_2608_17682_amd import synth, voro
@@ -169,7 +168,7 @@ def bench_config5(scene, dev, args, timed):
     sb = timed(fwdbwd, steps, 1)
     return {"workload": "shell4M: 2.8M shell + 1.2M uniform sites, 8x8 f16 texels, 8 mixed views "
                         "(2 pinhole 1280x840, 2 fisheye 1024^2, 2 rolling shutter 960x540, "
-                        "2 thin lens 640x480x4) in one persistent launch",
+                        "2 thin lens 640x480x4) in one launch",
             "rays": rays, "fwd_mrays_s": round(rays * steps / sf / 1e6, 2),
             "fwd_bwd_mrays_s": round(rays * steps / sb / 1e6, 2),
             "fwd_ms": round(sf * 1e3 / steps, 3), "fwd_bwd_ms": round(sb * 1e3 / steps, 3),
@@ -409,7 +408,8 @@ def main():
                    "morton": not args.no_morton,
                    "launch_fwd": {"lanes_per_ray": params.lanes_per_ray or 1,
                                   "tile": f"{params.tile_w or 8}x{params.tile_h or 8}",
-                                  "block": params.block or 256},
+                                  "block": params.block or 256,
+                                  "schedule": ["grid", "grid", "persistent"][params.schedule]},
                    "launch_source": "autotune table" if autotune.lookup("shell100k", "fwd")
                    and not (args.lanes_per_ray or args.tile) else "flags/defaults"},
         "roofline": roofline,
