@@ -106,7 +106,7 @@ typedef struct voro_scene {
   int32_t tex_res;   /* R in [VORO_MIN_TEX_RES, VORO_MAX_TEX_RES] */
   int32_t tex_dtype; /* VORO_TEX_* */
   int32_t reserved0; /* must be 0 */
-  int64_t n_edges;   /* M = nbr_off[N], < 2^31 */
+  int64_t n_edges;   /* M = nbr_off[N]; M + 3 N < 2^31 */
   const float* sites;
   const float* density;
   const int32_t* nbr_off;
@@ -194,7 +194,8 @@ voro_status voro_default_params(voro_params* p);
 /*
  * Bytes of device workspace the scene needs: packed cell records
  * (32 B per cell: position, density, adjacency row), packed edge records
- * (16 B per adjacency entry: p_j - p_i and j), the nearest-site search's
+ * (16 B per adjacency entry: (p_j - p_i)/|p_j - p_i|^2 and j, each row padded
+ * to a multiple of 4 entries, so at most M + 3 N records), the nearest-site search's
  * partial results and the persistent launch's work counters.  Host-only;
  * needs no device.
  */

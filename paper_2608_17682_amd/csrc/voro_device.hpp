@@ -18,9 +18,12 @@ constexpr float kInf = __builtin_huge_valf();
 // ----------------------------------------------------------- packed scene
 //
 // Cell record, 32 bytes = two float4: {x, y, z, sigma}, {edge_off, deg, 0, 0}
-// (the ints stored by bit pattern).  Edge record, 16 bytes: {n.x, n.y, n.z, j}
-// with n = p_j - p_i in FP32 and j the neighbour id (bit pattern).  A cell's
-// edges are contiguous, so one exit search reads deg consecutive float4s.
+// (the ints stored by bit pattern).  Edge record, 16 bytes: {m.x, m.y, m.z, j}
+// with m = n / |n|^2, n = p_j - p_i (the quotient formed in FP64 from the FP32
+// positions and rounded once) and j the neighbour id (bit pattern).  Row i
+// starts at edge_off = nbr_off[i] + 3 i and holds deg records followed by
+// null records {0, 0, 0, i} up to a multiple of 4, so an exit search reads
+// whole groups of four consecutive float4s.
 struct DevScene {
   const float4* __restrict__ cells;
   const float4* __restrict__ edges;
@@ -55,97 +58,81 @@ __device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, fl
 //
 // Among the Delaunay neighbours j of the current cell i, the ray leaves
 // through the bisector it reaches first moving forward (Sec. 3.1).  With
-// x_in = o + t_in w the entry point and q = x_in - p_i, the bisector of
-// (p_i, p_j) is crossed at t_in + (|n|^2/2 - n.q) / (n.w), n = p_j - p_i,
-// and only faces with n.w > 0 lie ahead.  Measuring from x_in keeps the
-// numerator small (cell-sized), and an error in t_in cancels: the result
-// is the plane's own crossing parameter.
+// x_in = o + t_in w the entry point, q = x_in - p_i and n = p_j - p_i, the
+// bisector of (p_i, p_j) is crossed at t_in + (|n|^2/2 - n.q) / (n.w), and
+// only faces with n.w > 0 lie ahead.  Measuring from x_in keeps the numerator
+// small (cell-sized), and an error in t_in cancels: the result is the plane's
+// own crossing parameter.  Dividing numerator and denominator by |n|^2, the
+// packed record m = n/|n|^2 gives u = (1 - m.(2q)) / (m.w), twice the
+// distance from t_in, in three FMAs, three FMAs and a reciprocal.
 //
-// The search keeps the best two candidates (t, j) in lexicographic order
-// (exact ties go to the smaller id), so the result does not depend on the
-// order or the lane split of the neighbour list.
-struct Top2 {
-  float t1;
-  int j1;
-  float t2;
-  int j2;
+// Inside a lane the search keeps the best u with its id and the second-best
+// u by value; lanes sharing a ray merge lexicographically in (u, id).  When
+// the best two lie within the tie window, every face whose FP32 crossing is
+// within the window of the best is re-decided in FP64 (exact ties to the
+// smaller id), so the result does not depend on the order or the lane split
+// of the neighbour list.
+struct Best {
+  float t1;  // best crossing offset
+  int j1;    // its neighbour (-1: none ahead)
+  float t2;  // second-best crossing offset (value only)
 };
 
-__device__ __forceinline__ bool lex_less(float ta, int ja, float tb, int jb) {
-  return (ta < tb) || (ta == tb && (unsigned)ja < (unsigned)jb);
+__device__ __forceinline__ float cross_u(const float4& E, float q2x, float q2y, float q2z,
+                                         float dx, float dy, float dz) {
+  const float b = dot3(E.x, E.y, E.z, dx, dy, dz);
+  const float a = fmaf(-E.z, q2z, fmaf(-E.y, q2y, fmaf(-E.x, q2x, 1.0f)));
+  return b > 0.0f ? a * __builtin_amdgcn_rcpf(b) : kInf;
 }
 
-__device__ __forceinline__ void top2_insert(Top2& r, float t, int j) {
-  if (lex_less(t, j, r.t1, r.j1)) {
-    r.t2 = r.t1;
-    r.j2 = r.j1;
-    r.t1 = t;
-    r.j1 = j;
-  } else if (lex_less(t, j, r.t2, r.j2)) {
-    r.t2 = t;
-    r.j2 = j;
-  }
+__device__ __forceinline__ void best_push(Best& r, float u, int j) {
+  const bool lt = u < r.t1;
+  r.t2 = __builtin_amdgcn_fmed3f(r.t1, r.t2, u);  // second smallest of {t1, t2, u}
+  r.t1 = lt ? u : r.t1;
+  r.j1 = lt ? j : r.j1;
 }
 
-// merge another lane's top two into r (both are sorted pairs)
-__device__ __forceinline__ void top2_merge(Top2& r, float u1, int k1, float u2, int k2) {
-  if (lex_less(u1, k1, r.t1, r.j1)) {
-    // other's best wins; second is min(r.first, other's second)
-    float s = r.t1;
-    int sj = r.j1;
-    if (lex_less(u2, k2, s, sj)) {
-      s = u2;
-      sj = k2;
-    }
-    r.t1 = u1;
-    r.j1 = k1;
-    r.t2 = s;
-    r.j2 = sj;
-  } else if (lex_less(u1, k1, r.t2, r.j2)) {
-    r.t2 = u1;
-    r.j2 = k1;
-  }
+// merge another lane's summary; symmetric, so both lanes of a pair agree
+__device__ __forceinline__ void best_merge(Best& r, float u1, int k1, float u2) {
+  const bool take = u1 < r.t1 || (u1 == r.t1 && (unsigned)k1 < (unsigned)r.j1);
+  const float loser = take ? r.t1 : u1;
+  const float s2 = u2 < r.t2 ? u2 : r.t2;
+  r.t2 = loser < s2 ? loser : s2;
+  r.t1 = take ? u1 : r.t1;
+  r.j1 = take ? k1 : r.j1;
 }
 
 template <int LPR>
-__device__ __forceinline__ Top2 exit_search(const float4* __restrict__ edges, int off, int deg,
+__device__ __forceinline__ Best exit_search(const float4* __restrict__ edges, int off, int deg,
                                             int sub, float qx, float qy, float qz, float dx,
                                             float dy, float dz) {
-  // Per neighbour: with n = p_j - p_i, a = n.(n - 2q) = 2(|n|^2/2 - n.q) and
-  // b = n.w, the crossing is t_in + a / (2b); the search compares u = a / b
-  // (twice the offset from t_in) and halves the winners.  Faces behind the
-  // ray (b <= 0) get u = +inf.  Inside a lane the best two are kept by value
-  // (an exact tie always falls inside the FP64 re-decision window); lanes
-  // sharing a ray merge lexicographically in (t, id).
   const float q2x = 2.0f * qx, q2y = 2.0f * qy, q2z = 2.0f * qz;
-  Top2 r;
+  Best r;
   r.t1 = kInf;
   r.j1 = -1;
   r.t2 = kInf;
-  r.j2 = -1;
   const float4* e = edges + off;
-#pragma unroll 4
-  for (int k = sub; k < deg; k += LPR) {
-    const float4 E = e[k];
-    const float b = dot3(E.x, E.y, E.z, dx, dy, dz);
-    const float a = dot3(E.x, E.y, E.z, E.x - q2x, E.y - q2y, E.z - q2z);
-    const float u = b > 0.0f ? a * __builtin_amdgcn_rcpf(b) : kInf;
-    const int j = __float_as_int(E.w);
-    const bool l1 = u < r.t1;
-    const bool l2 = u < r.t2;
-    r.t2 = l1 ? r.t1 : (l2 ? u : r.t2);
-    r.j2 = l1 ? r.j1 : (l2 ? j : r.j2);
-    r.t1 = l1 ? u : r.t1;
-    r.j1 = l1 ? j : r.j1;
-  }
-  if constexpr (LPR > 1) {
+  const int deg4 = (deg + 3) & ~3;
+  if constexpr (LPR == 1) {
+    for (int k = 0; k < deg4; k += 4) {
+      const float4 E0 = e[k], E1 = e[k + 1], E2 = e[k + 2], E3 = e[k + 3];
+      best_push(r, cross_u(E0, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E0.w));
+      best_push(r, cross_u(E1, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E1.w));
+      best_push(r, cross_u(E2, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E2.w));
+      best_push(r, cross_u(E3, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E3.w));
+    }
+  } else {
+#pragma unroll 2
+    for (int k = sub; k < deg4; k += LPR) {
+      const float4 E = e[k];
+      best_push(r, cross_u(E, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E.w));
+    }
 #pragma unroll
     for (int m = 1; m < LPR; m <<= 1) {
       const float u1 = __shfl_xor(r.t1, m);
       const int k1 = __shfl_xor(r.j1, m);
       const float u2 = __shfl_xor(r.t2, m);
-      const int k2 = __shfl_xor(r.j2, m);
-      top2_merge(r, u1, k1, u2, k2);
+      best_merge(r, u1, k1, u2);
     }
   }
   r.t1 *= 0.5f;
@@ -181,9 +168,11 @@ struct Exit {
   bool redecided;
 };
 
-__device__ __forceinline__ Exit decide_exit(const Top2& r, const float4* __restrict__ cells, int i,
-                                            float t_in, float tie_window, float ox, float oy,
-                                            float oz, float dx, float dy, float dz) {
+__device__ __forceinline__ Exit decide_exit(const Best& r, const float4* __restrict__ cells,
+                                            const float4* __restrict__ edges, int i, int off,
+                                            int deg, float t_in, float tie_window, float ox,
+                                            float oy, float oz, float dx, float dy, float dz,
+                                            float qx, float qy, float qz) {
   Exit x;
   x.redecided = false;
   if (r.j1 < 0) {
@@ -193,16 +182,26 @@ __device__ __forceinline__ Exit decide_exit(const Top2& r, const float4* __restr
   }
   x.t = t_in + r.t1;
   x.next = r.j1;
-  if (r.j2 >= 0 && (r.t2 - r.t1) <= tie_window * fmaxf(1.0f, fabsf(x.t))) {
-    const double t1 = cross64(cells, i, r.j1, ox, oy, oz, dx, dy, dz);
-    const double t2 = cross64(cells, i, r.j2, ox, oy, oz, dx, dy, dz);
-    double tb = t1;
-    int jb = r.j1;
-    if (t2 < t1 || (t2 == t1 && r.j2 < r.j1)) {
-      tb = t2;
-      jb = r.j2;
+  const float win = tie_window * fmaxf(1.0f, fabsf(x.t));
+  if (r.t2 - r.t1 <= win) {
+    // the same FP32 crossings as the search (halving is exact), so the best
+    // and the runner-up are always among the candidates
+    const float q2x = 2.0f * qx, q2y = 2.0f * qy, q2z = 2.0f * qz;
+    double tb = __builtin_huge_val();
+    int jb = -1;
+    for (int k = 0; k < deg; ++k) {
+      const float4 E = edges[off + k];
+      const float u = 0.5f * cross_u(E, q2x, q2y, q2z, dx, dy, dz);
+      if (u - r.t1 <= win) {
+        const int j = __float_as_int(E.w);
+        const double t = cross64(cells, i, j, ox, oy, oz, dx, dy, dz);
+        if (t < tb || (t == tb && t < __builtin_huge_val() && j < jb)) {
+          tb = t;
+          jb = j;
+        }
+      }
     }
-    if (tb < __builtin_huge_val()) {
+    if (jb >= 0) {
       x.t = (float)tb;
       x.next = jb;
     }
@@ -316,7 +315,9 @@ __device__ __forceinline__ Segment segment(float exit_t, float tmax, float t_in,
   Segment s;
   const float t_out = fminf(exit_t, tmax);
   s.delta = fmaxf(t_out - t_in, 0.0f);
-  s.trans = expf(-(sigma * s.delta));
+  // exp(-x) = 2^(-x log2 e) on the transcendental unit (relative error a
+  // few ulp, far inside the 1e-4 tolerance)
+  s.trans = __builtin_amdgcn_exp2f(-(sigma * s.delta) * 1.44269504088896341f);
   s.alpha = 1.0f - s.trans;
   return s;
 }

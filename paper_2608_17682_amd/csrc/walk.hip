@@ -16,7 +16,9 @@ namespace voro {
 
 // ------------------------------------------------------------------ prepare
 // 16 lanes per cell: lane 0 writes the cell record, all 16 stride over the
-// cell's adjacency row writing edge records (coalesced 256-byte runs).
+// cell's padded row writing edge records (coalesced 256-byte runs).  Row i
+// starts at nbr_off[i] + 3 i, so rows padded to a multiple of 4 never
+// overlap and no scan is needed.
 struct PrepArgs {
   const float* sites;
   const float* density;
@@ -38,29 +40,40 @@ __global__ void __launch_bounds__(256) k_prepare(PrepArgs a) {
   const int off = a.nbr_off[i];
   const int end = a.nbr_off[i + 1];
   const bool bad_row = off < 0 || end < off || end > a.m;
+  const int row = off + 3 * i;  // < m + 3 n < 2^31 (checked on the host)
+  const int deg = bad_row ? 0 : end - off;
   const float px = a.sites[3 * (size_t)i];
   const float py = a.sites[3 * (size_t)i + 1];
   const float pz = a.sites[3 * (size_t)i + 2];
   if (l16 == 0) {
     a.cells[2 * (size_t)i] = make_float4(px, py, pz, a.density[i]);
-    a.cells[2 * (size_t)i + 1] =
-        make_float4(__int_as_float(bad_row ? 0 : off), __int_as_float(bad_row ? 0 : end - off),
-                    0.0f, 0.0f);
+    a.cells[2 * (size_t)i + 1] = make_float4(__int_as_float(bad_row ? 0 : row),
+                                             __int_as_float(deg), 0.0f, 0.0f);
     if (bad_row && a.stats) atomicAdd(&a.stats[VORO_STAT_BAD_CSR], 1ull);
   }
   if (bad_row) return;
-  for (int e = off + l16; e < end; e += 16) {
-    const int j = a.nbr_idx[e];
-    float4 E;
-    if (j < 0 || j >= a.n || j == i) {
-      // never followed: n = 0 gives n.w = 0, which no exit search accepts
-      E = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(i));
-      if (a.stats) atomicAdd(&a.stats[VORO_STAT_BAD_CSR], 1ull);
-    } else {
-      E = make_float4(a.sites[3 * (size_t)j] - px, a.sites[3 * (size_t)j + 1] - py,
-                      a.sites[3 * (size_t)j + 2] - pz, __int_as_float(j));
+  const int deg4 = (deg + 3) & ~3;
+  for (int e = l16; e < deg4; e += 16) {
+    // null record: m = 0 gives m.w = 0, which no exit search accepts
+    float4 E = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(i));
+    if (e < deg) {
+      const int j = a.nbr_idx[off + e];
+      if (j < 0 || j >= a.n || j == i) {
+        if (a.stats) atomicAdd(&a.stats[VORO_STAT_BAD_CSR], 1ull);
+      } else {
+        const double nx = (double)a.sites[3 * (size_t)j] - (double)px;
+        const double ny = (double)a.sites[3 * (size_t)j + 1] - (double)py;
+        const double nz = (double)a.sites[3 * (size_t)j + 2] - (double)pz;
+        const double nn = nx * nx + ny * ny + nz * nz;
+        E.w = __int_as_float(j);
+        if (nn > 0.0) {  // coincident sites share no face: keep the null vector
+          E.x = (float)(nx / nn);
+          E.y = (float)(ny / nn);
+          E.z = (float)(nz / nn);
+        }
+      }
     }
-    a.edges[e] = E;
+    a.edges[row + e] = E;
   }
 }
 

@@ -69,8 +69,9 @@ __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w
   const float qx = fmaf(t_in, r.dx, r.ox) - c.px;
   const float qy = fmaf(t_in, r.dy, r.oy) - c.py;
   const float qz = fmaf(t_in, r.dz, r.oz) - c.pz;
-  const Top2 t2 = exit_search<LPR>(s.edges, c.off, c.deg, sub, qx, qy, qz, r.dx, r.dy, r.dz);
-  return decide_exit(t2, s.cells, cur, t_in, w.tie_window, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz);
+  const Best b = exit_search<LPR>(s.edges, c.off, c.deg, sub, qx, qy, qz, r.dx, r.dy, r.dz);
+  return decide_exit(b, s.cells, s.edges, cur, c.off, c.deg, t_in, w.tie_window, r.ox, r.oy, r.oz,
+                     r.dx, r.dy, r.dz, qx, qy, qz);
 }
 
 template <int LPR, int TEX>
