@@ -85,11 +85,15 @@ def oracle_sample(scene, cam, n_rays, workers, texels=None, seed=7):
 
 def bench_config3(scene, dev, args, timed):
     """2M sites on 20 ellipsoid surfaces, one 1280x840 interior pinhole view;
-    forward + backward through the autograd Function (FP32), upstream dL/dRGB
-    ~ N(0,1).  Step = rays + centre cell + prepare + forward + backward."""
+    forward + backward through the autograd Functions (FP32), upstream dL/dRGB
+    ~ N(0,1).  A step is what a training step spends on rendering: gradients
+    reset (as zero_grad(set_to_none=True) does), prepare, the forward launch,
+    dL/dsigma through sigma = exp(rho), and the backward launch.  Headline:
+    render_views (in-kernel ray generation, tuned launches); also reported:
+    render over explicit rays (ray generation + centre cell + both walks)."""
     import torch
-    from paper_2608_17682_amd import synth, voro
-    from paper_2608_17682_amd.autograd import render
+    from paper_2608_17682_amd import autotune, synth, voro
+    from paper_2608_17682_amd.autograd import render, render_views
     cam = synth.config3_camera(scene)
     ds0 = voro.device_scene(scene, dev)
     ds, perm, inv = voro.voro_morton_reorder(ds0)
@@ -99,8 +103,20 @@ def bench_config3(scene, dev, args, timed):
     tex = ds.texels.clone().requires_grad_(True)
     g = torch.from_numpy(synth.upstream(cam.n_rays, 3, with_gT=False)[0]).to(dev)
     ccam = [voro.camera_of(cam)]
+    pf, pb = autotune.params_for("config3", "fwd"), autotune.params_for("config3", "bwd")
 
-    def step():
+    def reset():
+        sites.grad = None
+        rho.grad = None
+        tex.grad = None
+
+    def step_views():
+        reset()
+        rgb, T = render_views(sites, torch.exp(rho), tex, ds.nbr_off, ds.nbr_idx, ccam, pf, pb)
+        (rgb * g).sum().backward()
+
+    def step_explicit():
+        reset()
         O, D, TM = voro.voro_gen_rays(ccam, dev)
         S = voro.voro_locate_origins(ds, O[:1]).expand(O.shape[0]).contiguous()
         rgb, T = render(sites, torch.exp(rho), tex, ds.nbr_off, ds.nbr_idx, O, D, TM, S,
@@ -110,18 +126,17 @@ def bench_config3(scene, dev, args, timed):
     # instrumented forward for the step counts
     st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
     voro.voro_prepare(ds)
-    O, D, TM = voro.voro_gen_rays(ccam, dev)
-    S = voro.voro_locate_origins(ds, O[:1]).expand(O.shape[0]).contiguous()
-    voro.voro_render_fwd(ds, O, D, TM, S, voro.default_params(img_w=cam.width), stats=st)
+    voro.voro_render_views_fwd(ds, ccam, pf, stats=st)
     stats = stats_dict(st)
     steps = max(2, args.steps // 2)
-    s = timed(step, steps, 1)
-    fwd_s = timed(lambda: voro.voro_render_fwd(ds, O, D, TM, S, voro.default_params(img_w=cam.width)),
-                  steps, 1)
+    s = timed(step_views, steps, 1)
+    se = timed(step_explicit, steps, 1)
+    fwd_s = timed(lambda: voro.voro_render_views_fwd(ds, ccam, pf), steps, 1)
     return {"workload": "ellipsoids2M: 1.8M sites on 20 ellipsoid surfaces (sigma 50) + 200k "
                         "uniform [-4,4]^3 (sigma 0.01), 8x8 f32 texels, 1280x840 interior "
                         "pinhole, tmax 14, fwd+bwd via torch.autograd.Function",
             "fwd_bwd_mrays_s": round(cam.n_rays * steps / s / 1e6, 2),
+            "fwd_bwd_explicit_rays_mrays_s": round(cam.n_rays * steps / se / 1e6, 2),
             "fwd_kernel_mrays_s": round(cam.n_rays * steps / fwd_s / 1e6, 2),
             "ms_per_step": round(s * 1e3 / steps, 3),
             "mean_cells_per_ray": round(stats["steps"] / max(1, stats["rays"]), 2)}

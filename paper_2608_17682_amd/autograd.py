@@ -1,12 +1,14 @@
-"""torch.autograd.Function over the HIP renderer.
+"""torch.autograd.Functions over the HIP renderer.
 
 ``render(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start)``
-returns (rgb [R,3], T [R]) and is differentiable with respect to the site
-positions, the densities sigma and the texels; rays and adjacency are not.
-The forward runs voro_prepare + voro_render_fwd; the backward runs
-voro_render_bwd, which replays each ray's walk instead of storing it.
-Parameterise sigma = exp(rho) in torch (Sec. 5.4) and autograd supplies
-dL/drho = sigma dL/dsigma.
+returns (rgb [R,3], T [R]) for explicit rays; ``render_views(sites, density,
+texels, nbr_off, nbr_idx, cameras)`` returns per-pixel (rgb [P,3], T [P])
+for up to 16 cameras generated in-kernel (one launch each way).  Both are
+differentiable with respect to the site positions, the densities sigma and
+the texels; rays, cameras and adjacency are not.  The forward runs
+voro_prepare + the forward walk; the backward replays each ray's walk
+instead of storing it.  Parameterise sigma = exp(rho) in torch (Sec. 5.4)
+and autograd supplies dL/drho = sigma dL/dsigma.
 """
 from __future__ import annotations
 
@@ -40,6 +42,48 @@ class VoroRender(torch.autograd.Function):
         if ctx.tex_dtype != torch.float32:
             gt = gt.to(ctx.tex_dtype)
         return gs, gd, gt, None, None, None, None, None, None, None
+
+
+class VoroRenderViews(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sites, density, texels, nbr_off, nbr_idx, cams, params_fwd, params_bwd):
+        ds = voro.DeviceScene(sites.detach().contiguous(), density.detach().contiguous(),
+                              nbr_off, nbr_idx, texels.detach().contiguous())
+        voro.voro_prepare(ds)
+        rgb, T, ray_rgbT = voro.voro_render_views_fwd(ds, cams, params_fwd)
+        ctx.ds = ds
+        ctx.cams = cams
+        ctx.params = params_bwd
+        ctx.tex_dtype = texels.dtype
+        ctx.ray_rgbT = ray_rgbT
+        ctx.save_for_backward(rgb, T)
+        return rgb, T
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_T):
+        rgb, T = ctx.saved_tensors
+        if g_rgb is None:
+            g_rgb = torch.zeros_like(rgb)
+        gs, gd, gt = voro.voro_render_views_bwd(
+            ctx.ds, ctx.cams, rgb, T, ctx.ray_rgbT, g_rgb.contiguous(),
+            None if g_T is None else g_T.contiguous(), ctx.params)
+        if ctx.tex_dtype != torch.float32:
+            gt = gt.to(ctx.tex_dtype)
+        return gs, gd, gt, None, None, None, None, None
+
+
+def render_views(sites, density, texels, nbr_off, nbr_idx, cams, params_fwd=None,
+                 params_bwd=None):
+    """Differentiable render of camera views (voro_camera list or objects with
+    the camera attributes); pixels of all views concatenated in order."""
+    cams = voro.camera_array(cams)
+    params_fwd = params_fwd or voro.default_params()
+    params_bwd = params_bwd or voro.default_params()
+    if params_fwd.skip_w != 0.0 and torch.is_grad_enabled() and (
+            sites.requires_grad or density.requires_grad or texels.requires_grad):
+        raise ValueError("skip_w must be 0 when gradients are needed")
+    return VoroRenderViews.apply(sites, density, texels, nbr_off, nbr_idx, cams, params_fwd,
+                                 params_bwd)
 
 
 def render(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params=None):

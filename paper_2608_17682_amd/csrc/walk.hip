@@ -67,9 +67,10 @@ __global__ void __launch_bounds__(256) k_prepare(PrepArgs a) {
         const double nn = nx * nx + ny * ny + nz * nz;
         E.w = __int_as_float(j);
         if (nn > 0.0) {  // coincident sites share no face: keep the null vector
-          E.x = (float)(nx / nn);
-          E.y = (float)(ny / nn);
-          E.z = (float)(nz / nn);
+          const double inv = 1.0 / nn;
+          E.x = (float)(nx * inv);
+          E.y = (float)(ny * inv);
+          E.z = (float)(nz * inv);
         }
       }
     }

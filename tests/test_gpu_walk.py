@@ -345,6 +345,44 @@ def test_views_bwd_equals_explicit(dev, c1):
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), name
 
 
+@pytest.mark.parametrize("schedule", [voro.SCHEDULE_GRID, voro.SCHEDULE_PERSISTENT])
+def test_autograd_views_equals_explicit(dev, c1, schedule):
+    # render_views (in-kernel rays, one launch each way) and render over the
+    # explicitly generated rays give the same image and the same gradients
+    from paper_2608_17682_amd.autograd import render as vrender, render_views
+    cams = synth.config5_cameras(scale=0.05)[:4]   # pinhole, fisheye, rolling shutter (spp 1)
+    for cm in cams:
+        cm.tmax = 4.0
+    nr = [cm.n_rays for cm in cams]
+    g_rgb, g_T = synth.upstream(sum(nr), 9)
+    Gr, Gt = to_dev(g_rgb, dev), to_dev(g_T, dev)
+    announce(f"autograd render_views vs render, schedule {schedule}")
+    leaves = []
+    for which in ("views", "explicit"):
+        sites = c1.ds.sites.clone().requires_grad_(True)
+        rho = torch.log(c1.ds.density.clone()).requires_grad_(True)
+        tex = c1.ds.texels.clone().requires_grad_(True)
+        if which == "views":
+            p = voro.default_params(schedule=schedule)
+            rgb, T = render_views(sites, torch.exp(rho), tex, c1.ds.nbr_off, c1.ds.nbr_idx, cams,
+                                  p, p)
+        else:
+            O, D, TM = voro.voro_gen_rays(cams, dev)
+            centres = to_dev(f32([cm.c2w[:, 3] for cm in cams]), dev)
+            cc = voro.voro_locate_origins(c1.ds, centres)
+            hint = torch.cat([cc[i:i + 1].expand(n) for i, n in enumerate(nr)]).contiguous()
+            S = voro.voro_locate_origins(c1.ds, O, hint=hint)
+            rgb, T = vrender(sites, torch.exp(rho), tex, c1.ds.nbr_off, c1.ds.nbr_idx, O, D, TM, S)
+        ((rgb * Gr).sum() + (T * Gt).sum()).backward()
+        leaves.append((rgb.detach().cpu().numpy(), T.detach().cpu().numpy(),
+                       sites.grad.cpu().numpy(), rho.grad.cpu().numpy(), tex.grad.cpu().numpy()))
+    (rv, tv, *gv), (re, te, *ge) = leaves
+    np.testing.assert_array_equal(rv, re)
+    np.testing.assert_array_equal(tv, te)
+    for a, b, name in zip(gv, ge, ("sites", "rho", "texels")):
+        assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), name
+
+
 @pytest.mark.parametrize("dtype", ["float16", "bfloat16"])
 def test_half_texels(dev, c1, dtype):
     announce(f"cast texels {dtype}")
