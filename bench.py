@@ -80,7 +80,9 @@ def oracle_sample(scene, cam, n_rays, workers, texels=None, seed=7):
     rgb, T, recs = render.render_rays_parallel(scene.sites, scene.density, tex, o32, d32, tm32,
                                                workers=workers, chunk=max(1, n_rays // workers))
     dt = time.perf_counter() - t0
-    return pick, rgb, T, dt
+    from oracle.margins import degenerate
+    degen = float(np.mean([degenerate(r) for r in recs]))
+    return pick, rgb, T, dt, degen
 
 
 def bench_config3(scene, dev, args, timed):
@@ -202,7 +204,7 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2M-site (fwd+bwd) and 4M-site (8 views) workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--oracle-rays", type=int, default=192)
+    ap.add_argument("--oracle-rays", type=int, default=1536)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -275,21 +277,27 @@ def main():
     rgb = torch.empty((npx, 3), device=dev)
     T = torch.empty(npx, device=dev)
 
-    def frame(i, p, dscene, out_rgb=rgb, out_T=T, stats=None):
-        voro.voro_render_views_fwd(dscene, [ccams[i]], p, rgb=out_rgb, T=out_T, stats=stats)
+    def frame(i, p, dscene, out_rgb=rgb, out_T=T, stats=None, nsteps=None):
+        voro.voro_render_views_fwd(dscene, [ccams[i]], p, rgb=out_rgb, T=out_T, stats=stats,
+                                   nsteps=nsteps)
 
     def step(dscene, p):
         voro.voro_prepare(dscene)
         for i in range(N_POSES):
             frame(i, p, dscene)
 
-    # instrumented pass (untimed): steps and degree sums for the byte model
+    # instrumented pass (untimed): steps and degree sums for the byte model,
+    # cells per ray over all poses
     st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    ks = torch.empty((N_POSES, rays_per_frame), dtype=torch.int32, device=dev)
     for i in range(N_POSES):
-        frame(i, params, ds, stats=st)
+        frame(i, params, ds, stats=st, nsteps=ks[i])
     torch.cuda.synchronize()
     stats = stats_dict(st)
-    log(f"stats per step: {stats}")
+    kq = torch.quantile(ks.flatten().float(), torch.tensor([0.5, 0.99], device=dev)).cpu().numpy()
+    k_dist = {"mean": round(float(ks.float().mean()), 2), "p50": float(kq[0]),
+              "p99": float(kq[1]), "max": int(ks.max())}
+    log(f"stats per step: {stats}; cells per ray {k_dist}")
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -335,7 +343,7 @@ def main():
                 "mean_cells_per_ray": round(stats["steps"] / max(1, stats["rays"]), 2),
                 "mean_degree": round(stats["degree_sum"] / max(1, stats["steps"]), 2)}
 
-    extras = {}
+    extras = {"cells_per_ray": k_dist, "fp64_redecisions_per_step": stats["fp64_redecide"]}
     if not args.no_extras:
         # half-precision texels (Sec. 5.6), FP32 compositing
         for name in ("float16", "bfloat16"):
@@ -375,7 +383,8 @@ def main():
 
     cpu_baseline = None
     if oracle_leg is not None:
-        workers, pick, rgb_o, T_o, dt = oracle_leg
+        workers, pick, rgb_o, T_o, dt, degen = oracle_leg
+        extras["oracle_sample_degenerate_ray_frac"] = degen
         # GPU colours of the same rays (pose 0, un-reordered scene) for the error report
         rgb0 = torch.empty((npx, 3), device=dev)
         T0 = torch.empty(npx, device=dev)
