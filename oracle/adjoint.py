@@ -26,6 +26,16 @@ constant: no gradient flows through tmax, early termination or max_steps.
 
 Under sigma = exp(rho) (Sec. 5.4) the caller's autograd multiplies by sigma,
 giving dL/drho = dL/dalpha (1 - alpha) ln(1/(1 - alpha)) per segment.
+
+Full appearance model (Sec. 5.2), c = sigmoid(l), l = T_vi(oct(d)) + T_vd(oct(-w)):
+    dL/dl           = w_k g * c (1 - c)                       (per channel)
+    dL/dtexel_q     += b_q dL/dl   for the taps of both maps
+    dL/dd           = sum_ch dL/dl_ch (dl_ch/du grad u + dl_ch/dv grad v)
+with (u, v) the octahedral coordinates of d and the taps held fixed.  With
+d = (x - p_i)/r, r = |x - p_i|, the hit point x = o + t_hit w gives
+    dL/dx = (I - d d^T) dL/dd / r,   dL/dp_i -= dL/dx,   dL/dt_hit = dL/dx . w,
+and t_hit moves with the crossing that defines it (the entry face, or the
+start cell's exit face), through the same dt/dp as above.
 """
 from __future__ import annotations
 
@@ -59,7 +69,14 @@ def grad_ray(sites, density, texels, o, w, tmax, rec, g_rgb, g_T, g_sites, g_den
     C = np.asarray(rec.rgb, np.float64)
     Tf = float(rec.T)
     K = rec.K
-    taps = appearance.bilinear_weights(w, res)
+    app = getattr(rec, "appearance", 0)
+    if app == 1:
+        res = texels.shape[2]
+        taps = appearance.bilinear_weights(-w, res)
+    else:
+        taps = appearance.bilinear_weights(w, res)
+    p64 = walk.as64(sites)
+    o64 = walk.as64(o)
     # suffix sums S_k = C - sum_{j<=k} w_j c_j
     prefix = np.zeros(3)
     entry_face = None  # (a, b, t) of the crossing that set the current entry
@@ -72,9 +89,36 @@ def grad_ray(sites, density, texels, o, w, tmax, rec, g_rgb, g_T, g_sites, g_den
         T_next = rec.T_before[k] * np.exp(-sig[i] * rec.delta[k])
         dtau = float(g @ (T_next * ck - S)) - gT * Tf
         g_density[i] += dtau * rec.delta[k]
-        if not rec.skipped[k]:
+        if not rec.skipped[k] and app == 0:
             for r, col, bw in taps:
                 g_texels[i, r, col, :3] += wk * bw * g
+        if not rec.skipped[k] and app == 1:
+            gl = wk * g * ck * (1.0 - ck)
+            d_surf = rec.surf_dir[k]
+            for r, col, bw in appearance.bilinear_weights(d_surf, res):
+                g_texels[i, 0, r, col, :3] += bw * gl
+            for r, col, bw in taps:
+                g_texels[i, 1, r, col, :3] += bw * gl
+            x = o64 + rec.t_hit[k] * w
+            rr = float(np.linalg.norm(x - p64[i]))
+            if rr > 0.0:
+                dcu, dcv = appearance.lookup_grad_uv(texels[i, 0], d_surf)
+                ju, jv = appearance.octahedral_jacobian(d_surf)
+                gd = float(gl @ dcu) * ju + float(gl @ dcv) * jv
+                gx = (gd - d_surf * float(d_surf @ gd)) / rr
+                g_sites[i] -= gx
+                dldt = float(gx @ w)
+                face = None
+                if k == 0:
+                    if rec.exit[0] < tmax and rec.nxt[0] >= 0:
+                        face = (i, rec.nxt[0], rec.exit[0])
+                elif entry_face is not None:
+                    face = entry_face
+                if face is not None:
+                    a, b, t = face
+                    da, db = face_dt_dsites(sites, a, b, o, w, t)
+                    g_sites[a] += dldt * da
+                    g_sites[b] += dldt * db
         if rec.delta[k] > 0.0:
             ddelta = sig[i] * dtau
             if entry_face is not None:
@@ -91,12 +135,12 @@ def grad_ray(sites, density, texels, o, w, tmax, rec, g_rgb, g_T, g_sites, g_den
 
 
 def grad_rays(sites, density, texels, origins, dirs, tmax, recs, g_rgb, g_T):
-    """Dense FP64 gradients summed over rays: (g_sites[N,3], g_density[N], g_texels[N,R,R,4])."""
+    """Dense FP64 gradients summed over rays: (g_sites[N,3], g_density[N], g_texels
+    shaped like texels: [N,R,R,4], or [N,2,R,R,4] for the full appearance model)."""
     N = len(sites)
-    res = texels.shape[1]
     gs = np.zeros((N, 3))
     gd = np.zeros(N)
-    gt = np.zeros((N, res, res, 4))
+    gt = np.zeros(np.shape(texels))
     tm = np.broadcast_to(np.asarray(tmax, np.float64), (len(origins),))
     for r, rec in enumerate(recs):
         if rec is None:

@@ -8,7 +8,15 @@ For the ordered segments k of the ray (one per visited cell i_k):
     C       = sum_k w_k c_k                             front-to-back colour
 
 with c_k the octahedral bilinear colour of cell i_k at the ray direction
-(Sec. 5.1).  Readings of what the paper leaves open:
+(Sec. 5.1; appearance 0), or, for the paper's full model (appearance 1,
+Sec. 5.2), c_k = sigmoid(T_vi(oct(d_k)) + T_vd(oct(-w))) with texels laid
+out [N, 2, R, R, 4] (map 0 = T_vi, map 1 = T_vd), d_k the unit direction from
+the site to the hit point x_k and -w the direction from x_k back towards
+the ray's origin.  Readings of what the paper leaves open:
+* the hit point is where the ray enters the cell, x_k = o + t_k w; in the
+  start cell, which holds the origin, it is where the ray leaves it,
+  o + min(exit_0, tmax) w; a hit point on the site itself (d undefined)
+  uses d = w;
 * early termination is tested strictly, T_{k+1} < t_stop, after segment k
   has been fully composited; the walk also ends at the first exit at or
   beyond tmax, and after max_steps segments (flagged);
@@ -26,7 +34,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import appearance, walk
+from . import appearance as appearance_mod, walk
 
 
 @dataclasses.dataclass
@@ -46,6 +54,9 @@ class RayRecord:
     gaps: List[float]        # FP64 gap between best and second-best exit, per step
     stop: str                # "tstop" | "tmax" | "max_steps"
     start_gap: float = math.inf
+    appearance: int = 0
+    t_hit: List[float] = dataclasses.field(default_factory=list)    # appearance 1
+    surf_dir: List[np.ndarray] = dataclasses.field(default_factory=list)
 
     @property
     def K(self) -> int:
@@ -53,11 +64,16 @@ class RayRecord:
 
 
 def render_ray(sites, density, texels, o, w, tmax, t_stop=1e-4, skip_w=0.0,
-               max_steps=4096, start=None, method="stepwise") -> RayRecord:
+               max_steps=4096, start=None, method="stepwise", appearance=0) -> RayRecord:
     """Render one ray by brute force.  method: 'stepwise' or 'interval'."""
+    appearance_model = int(appearance)
+    if appearance_model not in (0, 1):
+        raise ValueError(f"appearance {appearance}")
     sites = walk.as64(sites)
     sig = walk.as64(density)
     tex = np.asarray(texels)
+    if appearance_model == 1 and (tex.ndim != 5 or tex.shape[1] != 2):
+        raise ValueError("appearance 1 needs texels [N, 2, R, R, 4]")
     o = walk.as64(o)
     w = walk.as64(w)
     tmax = float(tmax)
@@ -82,7 +98,8 @@ def render_ray(sites, density, texels, o, w, tmax, t_stop=1e-4, skip_w=0.0,
     C = np.zeros(3)
     T = 1.0
     t = 0.0
-    rec = RayRecord(C, T, [], [], [], [], [], [], [], [], [], [], [], "tmax", start_gap)
+    rec = RayRecord(C, T, [], [], [], [], [], [], [], [], [], [], [], "tmax", start_gap,
+                    appearance)
     for k, (i, ex, j, gap) in enumerate(steps):
         t_out = min(ex, tmax)
         delta = max(t_out - t, 0.0)
@@ -90,10 +107,20 @@ def render_ray(sites, density, texels, o, w, tmax, t_stop=1e-4, skip_w=0.0,
         alpha = -math.expm1(-tau)
         wk = T * alpha
         skipped = skip_w > 0.0 and wk < skip_w
+        if appearance_model == 1:
+            t_hit = t if k > 0 else t_out
+            rel = o + t_hit * w - sites[i]
+            r = float(np.linalg.norm(rel))
+            d_surf = rel / r if r > 0.0 else w.copy()
+            rec.t_hit.append(t_hit)
+            rec.surf_dir.append(d_surf)
         if skipped:
             c = np.zeros(3)
         else:
-            c = appearance.lookup(tex[i], w)
+            if appearance_model == 1:
+                c = appearance_mod.full_colour(tex[i, 0], tex[i, 1], d_surf, -w)
+            else:
+                c = appearance_mod.lookup(tex[i], w)
             C = C + wk * c
         T_next = T * math.exp(-tau)
         rec.cells.append(i)
