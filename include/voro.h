@@ -99,13 +99,16 @@ enum {
  *   nbr_idx [M]   int32   CSR neighbour ids (no self loops)
  *   texels  [N,R,R,4]     per-cell octahedral texture, RGBA with A unused,
  *                         row index follows v, column index follows u;
- *                         float (16-byte aligned) or f16/bf16 (8-byte aligned)
+ *                         float (16-byte aligned) or f16/bf16 (8-byte aligned);
+ *           [N,2,R,R,4]   with tex_maps = 2: map 0 = surface map T_vi, map 1 =
+ *                         view map T_vd, both RGB logits (Sec. 5.1, 5.2;
+ *                         appearance 1)
  */
 typedef struct voro_scene {
   int32_t n_sites;   /* N >= 1 */
   int32_t tex_res;   /* R in [VORO_MIN_TEX_RES, VORO_MAX_TEX_RES] */
   int32_t tex_dtype; /* VORO_TEX_* */
-  int32_t reserved0; /* must be 0 */
+  int32_t tex_maps;  /* texture maps per cell: 0 or 1 = one, 2 = surface + view */
   int64_t n_edges;   /* M = nbr_off[N]; M + 3 N < 2^31 */
   const float* sites;
   const float* density;
@@ -122,7 +125,13 @@ typedef struct voro_scene {
  *   max_steps   cap on cells visited per ray (flagged in stats)         [4096]
  *   tie_window  exit faces whose FP32 crossings lie within
  *               tie_window * max(1, |t|) are re-decided in FP64          [1e-6]
- *   appearance  0 = single texture indexed by the ray direction          [0]
+ *   appearance  0 = single texture indexed by the ray direction, colour =
+ *               the interpolated texel (needs tex_maps 0 or 1)            [0]
+ *               1 = the full model of Sec. 5.1/5.2 (needs tex_maps = 2):
+ *               c = sigmoid(T_vi(oct(x - p_i)) + T_vd(oct(-d))), x the point
+ *               where the ray meets the cell - its entry point, or in the
+ *               start cell (which holds the origin) its exit point clipped
+ *               at tmax; x = p_i uses the ray direction instead of x - p_i
  *   lanes_per_ray  1, 2, 4, 8 or 16 lanes cooperate on one ray's
  *               neighbour tests (0 = library default)                   [0]
  *   tile_w, tile_h  screen tile walked by one 64-lane wave, in rays;
@@ -260,10 +269,12 @@ voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_b
  * nothing per step is stored between the passes.  Accumulates (+=, FP32
  * atomics) into
  *   g_sites [N,3], g_density [N] (dL/dsigma), g_texels [N,R,R,4] float
- *   (A channel untouched), whatever the texel storage type.
+ *   ([N,2,R,R,4] with tex_maps = 2; A channel untouched), whatever the
+ *   texel storage type.
  * g_T may be NULL (zero).  params.skip_w must be 0.  Gradients reach site
- * positions only through the crossing parameters of the bisector faces;
- * tmax, early termination and max_steps pass none.
+ * positions through the crossing parameters of the bisector faces and, with
+ * appearance 1, through the surface direction x - p_i (x moving with the
+ * crossing that places it); tmax, early termination and max_steps pass none.
  */
 voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_bytes,
                             const float* o, const float* d, const float* tmax,

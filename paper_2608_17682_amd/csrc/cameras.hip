@@ -155,7 +155,7 @@ __device__ __forceinline__ RayIn views_ray(const ViewsArgs& a, const TileRay& tr
 // PERSIST: waves loop over the XCD-partitioned tile queue; otherwise each
 // wave of the grid takes one tile (workgroups renumbered per XCD) and the
 // hardware dispatcher balances the load.
-template <int LPR, int TEX, bool PERSIST>
+template <int LPR, int TEX, int APP, bool PERSIST>
 __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
       bool capped = false;
       const RayIn r = views_ray(a, tr, &capped);
       capped_n += capped ? 1u : 0u;
-      const RayOut out = walk_forward<LPR, TEX>(a.s, a.w, r, sub, nullptr, 0, cnt);
+      const RayOut out = walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, nullptr, 0, cnt);
       if (sub == 0) {
         const voro_camera& c = a.ct.cam[tr.view];
         if (c.spp == 1) {
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
 // Backward work unit: a workgroup tile (the waves' tiles side by side, 2
 // wide), walked by the whole workgroup into one LDS gradient table that is
 // flushed to global memory before the next unit.
-template <int LPR, int TEX, bool PERSIST>
+template <int LPR, int TEX, int APP, bool PERSIST>
 __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -223,7 +223,9 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   __shared__ int s_unit;
   __shared__ int s_okeys[4][kOutbox];
   __shared__ float s_ovals[4][16 * kOutbox];
-  const GradTable tab{s_keys, s_vals};
+  GradTable tab;
+  tab.keys = s_keys;
+  tab.vals = s_vals;
   const Outbox ob{s_okeys[wave], s_ovals[wave]};
   table_clear(tab);
   Counters cnt;
@@ -268,7 +270,7 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
       u.gT = a.g_T ? a.g_T[p] * share : 0.0f;
     }
     // the whole wave walks its tile together (gradient records merge across lanes)
-    walk_backward<LPR, TEX>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, ob, cnt);
+    walk_backward<LPR, TEX, APP>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, ob, cnt);
     __syncthreads();
     table_flush(tab, a.g, RR, a.s.res);
     __syncthreads();
@@ -329,7 +331,7 @@ static CamTable make_table(const voro_camera* cams, int V, int tile_w, int tile_
   return ct;
 }
 
-template <int LPR, int TEX>
+template <int LPR, int TEX, int APP>
 static int persistent_blocks(bool backward, int block) {
   static int cached[2][3] = {};
   int& c = cached[backward ? 1 : 0][block == 64 ? 0 : (block == 128 ? 1 : 2)];
@@ -338,43 +340,53 @@ static int persistent_blocks(bool backward, int block) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (backward)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX, true>, block, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX, APP, true>, block, 0);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, true>, block, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block, 0);
   (void)hipGetLastError();
   c = max(kXcd, max(1, cus) * max(1, occ));
   c = (c / kXcd) * kXcd;
   return c;
 }
 
-template <int LPR, int TEX>
+template <int LPR, int TEX, int APP>
 static void launch_views_t(bool backward, bool persist, const ViewsArgs& a, int block,
                            hipStream_t st) {
   const int nwaves = block / 64;
   if (persist) {
-    const int blocks = persistent_blocks<LPR, TEX>(backward, block);
+    const int blocks = persistent_blocks<LPR, TEX, APP>(backward, block);
     if (backward)
-      hipLaunchKernelGGL((k_views_bwd<LPR, TEX, true>), dim3(blocks), dim3(block), 0, st, a);
+      hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
     else
-      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, true>), dim3(blocks), dim3(block), 0, st, a);
+      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
   } else if (backward) {
-    hipLaunchKernelGGL((k_views_bwd<LPR, TEX, false>), dim3(max(1, a.total_tiles)), dim3(block),
+    hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, false>), dim3(max(1, a.total_tiles)), dim3(block),
                        0, st, a);
   } else {
     const int blocks = max(1, (a.total_tiles + nwaves - 1) / nwaves);
-    hipLaunchKernelGGL((k_views_fwd<LPR, TEX, false>), dim3(blocks), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block), 0, st, a);
   }
 }
 
-template <int TEX>
+template <int TEX, int APP>
 static void launch_views_lpr(int lpr, bool backward, bool persist, const ViewsArgs& a, int block,
                              hipStream_t st) {
   switch (lpr) {
-    case 1: launch_views_t<1, TEX>(backward, persist, a, block, st); break;
-    case 2: launch_views_t<2, TEX>(backward, persist, a, block, st); break;
-    case 4: launch_views_t<4, TEX>(backward, persist, a, block, st); break;
-    case 8: launch_views_t<8, TEX>(backward, persist, a, block, st); break;
-    default: launch_views_t<16, TEX>(backward, persist, a, block, st); break;
+    case 1: launch_views_t<1, TEX, APP>(backward, persist, a, block, st); break;
+    case 2: launch_views_t<2, TEX, APP>(backward, persist, a, block, st); break;
+    case 4: launch_views_t<4, TEX, APP>(backward, persist, a, block, st); break;
+    case 8: launch_views_t<8, TEX, APP>(backward, persist, a, block, st); break;
+    default: launch_views_t<16, TEX, APP>(backward, persist, a, block, st); break;
+  }
+}
+
+template <int APP>
+static void launch_views_tex(int tex, int lpr, bool backward, bool persist, const ViewsArgs& a,
+                             int block, hipStream_t st) {
+  switch (tex) {
+    case VORO_TEX_F32: launch_views_lpr<VORO_TEX_F32, APP>(lpr, backward, persist, a, block, st); break;
+    case VORO_TEX_F16: launch_views_lpr<VORO_TEX_F16, APP>(lpr, backward, persist, a, block, st); break;
+    default: launch_views_lpr<VORO_TEX_BF16, APP>(lpr, backward, persist, a, block, st); break;
   }
 }
 
@@ -386,6 +398,7 @@ static voro_status views_common(bool backward, const voro_scene* scene, void* ws
   if ((st = check_scene(scene)) != VORO_OK) return st;
   if ((st = check_ws(scene, ws, ws_bytes)) != VORO_OK) return st;
   if ((st = check_params(params, backward)) != VORO_OK) return st;
+  if ((st = check_appearance(scene, params)) != VORO_OK) return st;
   if ((st = check_cameras(cams, V, n_rays, n_pixels)) != VORO_OK) return st;
   bool spp = false;
   for (int v = 0; v < V; ++v) spp = spp || cams[v].spp > 1;
@@ -421,11 +434,10 @@ static voro_status views_common(bool backward, const voro_scene* scene, void* ws
   if ((st = launch_locate_brute(scene, ws, origins, V, centers, s)) != VORO_OK) return st;
   const int block = L.block;
   const bool persist = params->schedule == VORO_SCHEDULE_PERSISTENT;
-  switch (scene->tex_dtype) {
-    case VORO_TEX_F32: launch_views_lpr<VORO_TEX_F32>(L.lpr, backward, persist, a, block, s); break;
-    case VORO_TEX_F16: launch_views_lpr<VORO_TEX_F16>(L.lpr, backward, persist, a, block, s); break;
-    default: launch_views_lpr<VORO_TEX_BF16>(L.lpr, backward, persist, a, block, s); break;
-  }
+  if (params->appearance == 1)
+    launch_views_tex<1>(scene->tex_dtype, L.lpr, backward, persist, a, block, s);
+  else
+    launch_views_tex<0>(scene->tex_dtype, L.lpr, backward, persist, a, block, s);
   return check_launch(backward ? "voro_render_views_bwd" : "voro_render_views_fwd");
 }
 
@@ -506,6 +518,7 @@ voro_status voro_render_views_bwd(const voro_scene* scene, void* ws, size_t ws_b
   a.g.sites = g_sites;
   a.g.density = g_density;
   a.g.texels = g_texels;
+  a.g.maps = scene && scene->tex_maps == 2 ? 2 : 1;
   a.stats = reinterpret_cast<unsigned long long*>(stats);
   bool any_spp = false;
   return views_common(true, scene, ws, ws_bytes, cams, V, params, a, &nr, &np, &any_spp, stream);

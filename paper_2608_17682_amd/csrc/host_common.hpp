@@ -42,6 +42,7 @@ inline WsLayout ws_layout(int32_t n, int64_t m) {
 voro_status check_scene(const voro_scene* s);
 voro_status check_ws(const voro_scene* s, const void* ws, size_t ws_bytes);
 voro_status check_params(const voro_params* p, bool backward);
+voro_status check_appearance(const voro_scene* s, const voro_params* p);
 voro_status check_cameras(const voro_camera* cams, int32_t V, int64_t* n_rays, int64_t* n_pixels);
 voro_status check_device();
 voro_status check_launch(const char* what);

@@ -301,6 +301,67 @@ __device__ __forceinline__ void texel_rgb(const void* __restrict__ tex, int i, i
   b = fmaf(tp.w11, f.z, fmaf(tp.w10, e.z, fmaf(tp.w01, c.z, tp.w00 * a.z)));
 }
 
+// ------------------------------------------------ full appearance model
+//
+// Sec. 5.1/5.2: each cell holds two maps of RGB logits, [N, 2, R, R, 4]
+// (map 0 = surface map, map 1 = view map); the colour is sigmoid(surface
+// map at oct(x - p_i) + view map at oct(-w)), x the point where the ray
+// meets the cell (its entry point; the exit point in the start cell).  The
+// octahedral map is unchanged by positive scaling, so the surface taps take
+// x - p_i as it is.
+
+constexpr float kLog2e = 1.44269504088896341f;
+
+__device__ __forceinline__ float sigmoid_f(float l) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-l * kLog2e));
+}
+
+// logits of cell i: surface map at taps ts (its four texels returned for the
+// adjoint), view map at taps tv
+template <int TEX>
+__device__ __forceinline__ void full_logits(const void* __restrict__ tex, int i, int R,
+                                            const Taps& ts, const Taps& tv, float& lr, float& lg,
+                                            float& lb, float4& a, float4& b, float4& e,
+                                            float4& f) {
+  const size_t base = (size_t)(2 * i) * (size_t)(R * R) + (size_t)ts.base;
+  a = TexelT<TEX>::load(tex, base);
+  b = TexelT<TEX>::load(tex, base + 1);
+  e = TexelT<TEX>::load(tex, base + R);
+  f = TexelT<TEX>::load(tex, base + R + 1);
+  float vr, vg, vb;
+  texel_rgb<TEX>(tex, 2 * i + 1, R, tv, vr, vg, vb);
+  lr = fmaf(ts.w11, f.x, fmaf(ts.w10, e.x, fmaf(ts.w01, b.x, ts.w00 * a.x))) + vr;
+  lg = fmaf(ts.w11, f.y, fmaf(ts.w10, e.y, fmaf(ts.w01, b.y, ts.w00 * a.y))) + vg;
+  lb = fmaf(ts.w11, f.z, fmaf(ts.w10, e.z, fmaf(ts.w01, b.z, ts.w00 * a.z))) + vb;
+}
+
+// d(u, v)/d(d) of the octahedral map at any direction d != 0: with
+// s = |d|_1, q = d/s, dq_a/dd = (e_a - q_a sgn d)/s (sgn(0) = +1); upper
+// hemisphere (u, v) = (qx, qy); lower du = -sgn qx sgn qy dqy and
+// dv = -sgn qx sgn qy dqx.
+__device__ __forceinline__ void oct_jacobian(float dx, float dy, float dz, float ju[3],
+                                             float jv[3]) {
+  const float inv = 1.0f / (fabsf(dx) + fabsf(dy) + fabsf(dz));
+  const float qx = dx * inv, qy = dy * inv;
+  const float sx = sgn_nz(dx), sy = sgn_nz(dy), sz = sgn_nz(dz);
+  const float ax[3] = {(1.0f - qx * sx) * inv, -qx * sy * inv, -qx * sz * inv};
+  const float ay[3] = {-qy * sx * inv, (1.0f - qy * sy) * inv, -qy * sz * inv};
+  if (dz >= 0.0f) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ju[k] = ax[k];
+      jv[k] = ay[k];
+    }
+  } else {
+    const float m = -sx * sy;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ju[k] = m * ay[k];
+      jv[k] = m * ax[k];
+    }
+  }
+}
+
 // ---------------------------------------------------------- segment math
 //
 // Sec. 3.2: delta = max(min(exit, tmax) - t_in, 0), alpha = 1 - exp(-sigma

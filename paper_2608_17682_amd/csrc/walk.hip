@@ -102,7 +102,7 @@ struct RayArgs {
   unsigned long long* stats;
 };
 
-template <int LPR, int TEX>
+template <int LPR, int TEX, int APP>
 __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
   const int nwaves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
     r.start = a.start[ray];
     int32_t* rec = (a.cells_out && a.max_record > 0) ? a.cells_out + (size_t)ray * a.max_record
                                                      : nullptr;
-    const RayOut out = walk_forward<LPR, TEX>(a.s, a.w, r, sub, rec, a.max_record, cnt);
+    const RayOut out = walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, rec, a.max_record, cnt);
     if (sub == 0) {
       a.rgb[3 * (size_t)ray] = out.r;
       a.rgb[3 * (size_t)ray + 1] = out.g;
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
 }
 
-template <int LPR, int TEX>
+template <int LPR, int TEX, int APP>
 __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
   const int nwaves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
@@ -172,46 +172,57 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
   __shared__ float s_vals[16 * kTableCap];
   __shared__ int s_okeys[4][kOutbox];
   __shared__ float s_ovals[4][16 * kOutbox];
-  const GradTable tab{s_keys, s_vals};
+  GradTable tab;
+  tab.keys = s_keys;
+  tab.vals = s_vals;
   const Outbox ob{s_okeys[wave], s_ovals[wave]};
   table_clear(tab);
   __syncthreads();
   // all lanes take part: the gradient records are merged across the wave,
   // then across the workgroup in the LDS table
-  walk_backward<LPR, TEX>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, ob, cnt);
+  walk_backward<LPR, TEX, APP>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, ob, cnt);
   __syncthreads();
   table_flush(tab, a.g, a.s.res * a.s.res, a.s.res);
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
 }
 
-template <int LPR, int TEX>
+template <int LPR, int TEX, int APP>
 static void launch_ray_kernel(bool backward, const RayArgs& a, int blocks, int block,
                               hipStream_t st) {
   if (backward)
-    hipLaunchKernelGGL((k_render_bwd<LPR, TEX>), dim3(blocks), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_render_bwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
   else
-    hipLaunchKernelGGL((k_render_fwd<LPR, TEX>), dim3(blocks), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
 }
 
-template <int TEX>
+template <int TEX, int APP>
 static void dispatch_lpr(int lpr, bool backward, const RayArgs& a, int blocks, int block,
                          hipStream_t st) {
   switch (lpr) {
-    case 1: launch_ray_kernel<1, TEX>(backward, a, blocks, block, st); break;
-    case 2: launch_ray_kernel<2, TEX>(backward, a, blocks, block, st); break;
-    case 4: launch_ray_kernel<4, TEX>(backward, a, blocks, block, st); break;
-    case 8: launch_ray_kernel<8, TEX>(backward, a, blocks, block, st); break;
-    default: launch_ray_kernel<16, TEX>(backward, a, blocks, block, st); break;
+    case 1: launch_ray_kernel<1, TEX, APP>(backward, a, blocks, block, st); break;
+    case 2: launch_ray_kernel<2, TEX, APP>(backward, a, blocks, block, st); break;
+    case 4: launch_ray_kernel<4, TEX, APP>(backward, a, blocks, block, st); break;
+    case 8: launch_ray_kernel<8, TEX, APP>(backward, a, blocks, block, st); break;
+    default: launch_ray_kernel<16, TEX, APP>(backward, a, blocks, block, st); break;
   }
 }
 
-static void dispatch_ray_kernel(int tex, int lpr, bool backward, const RayArgs& a, int blocks,
-                                int block, hipStream_t st) {
+template <int APP>
+static void dispatch_tex(int tex, int lpr, bool backward, const RayArgs& a, int blocks, int block,
+                         hipStream_t st) {
   switch (tex) {
-    case VORO_TEX_F32: dispatch_lpr<VORO_TEX_F32>(lpr, backward, a, blocks, block, st); break;
-    case VORO_TEX_F16: dispatch_lpr<VORO_TEX_F16>(lpr, backward, a, blocks, block, st); break;
-    default: dispatch_lpr<VORO_TEX_BF16>(lpr, backward, a, blocks, block, st); break;
+    case VORO_TEX_F32: dispatch_lpr<VORO_TEX_F32, APP>(lpr, backward, a, blocks, block, st); break;
+    case VORO_TEX_F16: dispatch_lpr<VORO_TEX_F16, APP>(lpr, backward, a, blocks, block, st); break;
+    default: dispatch_lpr<VORO_TEX_BF16, APP>(lpr, backward, a, blocks, block, st); break;
   }
+}
+
+static void dispatch_ray_kernel(int app, int tex, int lpr, bool backward, const RayArgs& a,
+                                int blocks, int block, hipStream_t st) {
+  if (app == 1)
+    dispatch_tex<1>(tex, lpr, backward, a, blocks, block, st);
+  else
+    dispatch_tex<0>(tex, lpr, backward, a, blocks, block, st);
 }
 
 DevScene dev_scene(const voro_scene* s, const void* ws) {
@@ -242,6 +253,7 @@ static voro_status ray_launch(bool backward, const voro_scene* scene, const void
   if ((st = check_scene(scene)) != VORO_OK) return st;
   if ((st = check_ws(scene, ws, ws_bytes)) != VORO_OK) return st;
   if ((st = check_params(params, backward)) != VORO_OK) return st;
+  if ((st = check_appearance(scene, params)) != VORO_OK) return st;
   if (R < 0) return fail(VORO_EINVAL, "R must be >= 0");
   if (R == 0) return VORO_OK;
   if (!o || !d || !tmax || !start) return fail(VORO_EINVAL, "ray arrays must not be NULL");
@@ -274,7 +286,7 @@ static voro_status ray_launch(bool backward, const voro_scene* scene, const void
     blocks = (R + rays_per_block - 1) / rays_per_block;
   }
   if (blocks > 0x7fffffff) return fail(VORO_EINVAL, "too many rays");
-  dispatch_ray_kernel(scene->tex_dtype, L.lpr, backward, a, (int)blocks, L.block,
+  dispatch_ray_kernel(params->appearance, scene->tex_dtype, L.lpr, backward, a, (int)blocks, L.block,
                       (hipStream_t)stream);
   return check_launch(backward ? "voro_render_bwd" : "voro_render_fwd");
 }
@@ -345,6 +357,7 @@ voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_b
   a.g.sites = g_sites;
   a.g.density = g_density;
   a.g.texels = g_texels;
+  a.g.maps = scene && scene->tex_maps == 2 ? 2 : 1;
   a.stats = reinterpret_cast<unsigned long long*>(stats);
   return ray_launch(true, scene, ws, ws_bytes, o, d, tmax, start_cell, R, params, a, stream);
 }

@@ -38,7 +38,8 @@ struct Upstream {
 struct Grads {
   float* sites;    // [N,3]
   float* density;  // [N]
-  float* texels;   // [N,R,R,4]
+  float* texels;   // [N,R,R,4], or [N,2,R,R,4] for the full appearance model
+  int maps;        // texture maps per cell (1 or 2)
 };
 
 struct Counters {
@@ -74,7 +75,25 @@ __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w
                      r.dx, r.dy, r.dz, qx, qy, qz);
 }
 
-template <int LPR, int TEX>
+// Full appearance model: the vector from the site to the point where the ray
+// meets cell c (its entry point t_in; the clipped exit point in the start
+// cell, step k = 0).  Zero when that point is the site itself.
+__device__ __forceinline__ void hit_vector(const RayIn& r, const Cell& c, int k, float t_in,
+                                           float exit_t, float& hx, float& hy, float& hz) {
+  const float th = k > 0 ? t_in : fminf(exit_t, r.tmax);
+  hx = fmaf(th, r.dx, r.ox) - c.px;
+  hy = fmaf(th, r.dy, r.oy) - c.py;
+  hz = fmaf(th, r.dz, r.oz) - c.pz;
+}
+
+// The taps a ray uses for every cell: the single map at +w (appearance 0)
+// or the view map at -w (appearance 1).
+template <int APP>
+__device__ __forceinline__ Taps ray_taps(const RayIn& r, int R) {
+  return APP ? make_taps(-r.dx, -r.dy, -r.dz, R) : make_taps(r.dx, r.dy, r.dz, R);
+}
+
+template <int LPR, int TEX, int APP>
 __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkParams& w,
                                                const RayIn& r, int sub, int32_t* rec,
                                                int max_record, Counters& cnt) {
@@ -88,7 +107,7 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
     return out;
   }
   cnt.rays++;
-  const Taps tp = make_taps(r.dx, r.dy, r.dz, s.res);
+  const Taps tp = ray_taps<APP>(r, s.res);
   float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, t_in = 0.0f;
   int cur = r.start;
   int k = 0;
@@ -101,7 +120,21 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
     const float wk = T * sg.alpha;
     if (wk >= w.skip_w) {
       float cr, cg, cb;
-      texel_rgb<TEX>(s.texels, cur, s.res, tp, cr, cg, cb);
+      if constexpr (APP == 0) {
+        texel_rgb<TEX>(s.texels, cur, s.res, tp, cr, cg, cb);
+      } else {
+        float hx, hy, hz;
+        hit_vector(r, c, k, t_in, ex.t, hx, hy, hz);
+        const bool on_site = hx == 0.0f && hy == 0.0f && hz == 0.0f;
+        const Taps ts = make_taps(on_site ? r.dx : hx, on_site ? r.dy : hy,
+                                  on_site ? r.dz : hz, s.res);
+        float lr, lg, lb;
+        float4 ta, tb, te, tf;
+        full_logits<TEX>(s.texels, cur, s.res, ts, tp, lr, lg, lb, ta, tb, te, tf);
+        cr = sigmoid_f(lr);
+        cg = sigmoid_f(lg);
+        cb = sigmoid_f(lb);
+      }
       Cr = fmaf(wk, cr, Cr);
       Cg = fmaf(wk, cg, Cg);
       Cb = fmaf(wk, cb, Cb);
@@ -159,16 +192,18 @@ __device__ __forceinline__ void atomic_site(const Grads& g, int cell, float x, f
   atomicAdd(&g.sites[3 * (size_t)cell + 2], z);
 }
 
-// Address of term c (0..15) of a record: 0 dsigma, 1-3 dp, 4-15 the texel
-// terms of taps (r0,c0), (r0,c0+1), (r0+1,c0), (r0+1,c0+1) x RGB.
+// A record's key is (cell * maps + map) * R^2 + texel quad.  Address of term
+// c (0..15): 0 dsigma, 1-3 dp, 4-15 the texel terms of taps (r0,c0),
+// (r0,c0+1), (r0+1,c0), (r0+1,c0+1) x RGB of that map.
 __device__ __forceinline__ float* record_addr(const Grads& g, int key, int c, int RR, int R) {
-  const int cell = key / RR;
-  const int base = key - cell * RR;
+  const int cm = key / RR;
+  const int base = key - cm * RR;
+  const int cell = g.maps == 2 ? (cm >> 1) : cm;
   if (c == 0) return g.density + cell;
   if (c < 4) return g.sites + 3 * (size_t)cell + (c - 1);
   const int t = (c - 4) / 3;
   const int ch = (c - 4) - 3 * t;
-  return g.texels + ((size_t)cell * (size_t)RR + (size_t)base) * 4 + (t & 1) * 4 + (t >> 1) * 4 * R +
+  return g.texels + ((size_t)cm * (size_t)RR + (size_t)base) * 4 + (t & 1) * 4 + (t >> 1) * 4 * R +
          ch;
 }
 
@@ -267,22 +302,23 @@ __device__ __forceinline__ void table_flush(const GradTable& t, const Grads& g, 
 // for m = LPR .. 32), then add the survivors to the workgroup table (or, with
 // no table, to global memory).  Every lane of the wave must call this (key <
 // 0: no record).
+// The texel term of tap t and channel ch is tap weight t x m_ch.
 template <int LPR>
-__device__ __forceinline__ void emit_records(int key, float ds, float px, float py, float pz, float w,
-                                             const Taps& tp, const Upstream& u, int lane, int RR,
-                                             int R, const Grads& g, const GradTable* tab,
+__device__ __forceinline__ void emit_records(int key, float ds, float px, float py, float pz,
+                                             const Taps& tp, float mr, float mg, float mb, int lane,
+                                             int RR, int R, const Grads& g, const GradTable* tab,
                                              const Outbox& ob) {
   float v[16];
   v[0] = ds;
   v[1] = px;
   v[2] = py;
   v[3] = pz;
-  const float q[4] = {w * tp.w00, w * tp.w01, w * tp.w10, w * tp.w11};
+  const float q[4] = {tp.w00, tp.w01, tp.w10, tp.w11};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    v[4 + 3 * t] = q[t] * u.gr;
-    v[5 + 3 * t] = q[t] * u.gg;
-    v[6 + 3 * t] = q[t] * u.gb;
+    v[4 + 3 * t] = q[t] * mr;
+    v[5 + 3 * t] = q[t] * mg;
+    v[6 + 3 * t] = q[t] * mb;
   }
 #pragma unroll
   for (int m = LPR; m < 64; m <<= 1) {
@@ -308,13 +344,22 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
 // Every lane of the wave must call this; has_ray = false for lanes without a
 // ray.  The loop runs until every lane's walk has ended, so the record merge
 // always sees the full wave.
-template <int LPR, int TEX>
+//
+// Full appearance model (APP = 1): with c = sigmoid(l), dL/dl = w_k g c(1-c)
+// per channel feeds the surface-map taps (in the cell's delayed record) and
+// the view-map taps (a record of its own, sent at once).  The surface
+// direction adds dL/dx = J^T dL/d(u,v) for the hit point x, J the
+// octahedral map's Jacobian at x - p_i: -dL/dx goes to the site, and
+// dL/dt_hit = dL/dx . w to the crossing that placed x (the entry face, or
+// the start cell's exit face) through the same dt/dp as the segment ends.
+template <int LPR, int TEX, int APP>
 __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParams& w, const RayIn& r,
                                               const Upstream& u, bool has_ray, int sub, int lane,
                                               const Grads& g, const GradTable* tab,
                                               const Outbox& ob, Counters& cnt) {
   const int R = s.res;
   const int RR = R * R;
+  constexpr int MAPS = APP ? 2 : 1;
   bool active = has_ray && r.tmax > 0.0f;
   if (active && (r.start < 0 || r.start >= s.n)) {
     cnt.bad++;
@@ -322,13 +367,16 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
   }
   if (active) cnt.rays++;
   const bool lead = sub == 0;
-  const Taps tp = make_taps(r.dx, r.dy, r.dz, R);
+  const Taps tp = ray_taps<APP>(r, R);
   float T = 1.0f, Pr = 0.0f, Pg = 0.0f, Pb = 0.0f, t_in = 0.0f;
   int cur = active ? r.start : 0;
   int k = 0;
-  // previous cell's record (emitted one step late)
+  // previous cell's record (emitted one step late): its texel multipliers
+  // and, for APP = 1, its surface taps
   int a_cell = -1;
-  float a_ds = 0.0f, a_px = 0.0f, a_py = 0.0f, a_pz = 0.0f, a_w = 0.0f;
+  float a_ds = 0.0f, a_px = 0.0f, a_py = 0.0f, a_pz = 0.0f;
+  float a_mr = 0.0f, a_mg = 0.0f, a_mb = 0.0f;
+  Taps a_tp = tp;
   // position gradient already received by the cell entered next
   int c_cell = -1;
   float c_px = 0.0f, c_py = 0.0f, c_pz = 0.0f;
@@ -338,7 +386,11 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
   for (;;) {
     if (!__any(active)) break;
     int e_key = -1;
-    float e_ds = 0.0f, e_px = 0.0f, e_py = 0.0f, e_pz = 0.0f, e_w = 0.0f;
+    float e_ds = 0.0f, e_px = 0.0f, e_py = 0.0f, e_pz = 0.0f;
+    float e_mr = 0.0f, e_mg = 0.0f, e_mb = 0.0f;
+    Taps e_tp = tp;
+    int v_key = -1;  // APP = 1: this cell's view-map record
+    float v_mr = 0.0f, v_mg = 0.0f, v_mb = 0.0f;
     if (active) {
       const Cell c = load_cell(s.cells, cur);
       const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
@@ -347,7 +399,46 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
       const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
       const float wk = T * sg.alpha;
       float cr, cg, cb;
-      texel_rgb<TEX>(s.texels, cur, R, tp, cr, cg, cb);
+      Taps ts = tp;
+      float gxx = 0.0f, gxy = 0.0f, gxz = 0.0f, dldt = 0.0f;
+      float glr = 0.0f, glg = 0.0f, glb = 0.0f;
+      if constexpr (APP == 0) {
+        texel_rgb<TEX>(s.texels, cur, R, tp, cr, cg, cb);
+      } else {
+        float hx, hy, hz;
+        hit_vector(r, c, k, t_in, ex.t, hx, hy, hz);
+        const bool on_site = hx == 0.0f && hy == 0.0f && hz == 0.0f;
+        ts = make_taps(on_site ? r.dx : hx, on_site ? r.dy : hy, on_site ? r.dz : hz, R);
+        float lr, lg, lb;
+        float4 ta, tb, te, tf;
+        full_logits<TEX>(s.texels, cur, R, ts, tp, lr, lg, lb, ta, tb, te, tf);
+        cr = sigmoid_f(lr);
+        cg = sigmoid_f(lg);
+        cb = sigmoid_f(lb);
+        glr = wk * u.gr * cr * (1.0f - cr);
+        glg = wk * u.gg * cg * (1.0f - cg);
+        glb = wk * u.gb * cb * (1.0f - cb);
+        if (!on_site) {
+          // dL/d(u,v) of the bilinear surface lookup (taps held fixed)
+          const float kR = 0.5f * (float)(R - 1);
+          const float fx = ts.w01 + ts.w11;
+          const float fy = ts.w10 + ts.w11;
+          const float dur = kR * fmaf(fy, tf.x - te.x, (1.0f - fy) * (tb.x - ta.x));
+          const float dug = kR * fmaf(fy, tf.y - te.y, (1.0f - fy) * (tb.y - ta.y));
+          const float dub = kR * fmaf(fy, tf.z - te.z, (1.0f - fy) * (tb.z - ta.z));
+          const float dvr = kR * fmaf(fx, tf.x - tb.x, (1.0f - fx) * (te.x - ta.x));
+          const float dvg = kR * fmaf(fx, tf.y - tb.y, (1.0f - fx) * (te.y - ta.y));
+          const float dvb = kR * fmaf(fx, tf.z - tb.z, (1.0f - fx) * (te.z - ta.z));
+          const float gu = dot3(glr, glg, glb, dur, dug, dub);
+          const float gv = dot3(glr, glg, glb, dvr, dvg, dvb);
+          float ju[3], jv[3];
+          oct_jacobian(hx, hy, hz, ju, jv);
+          gxx = fmaf(gu, ju[0], gv * jv[0]);
+          gxy = fmaf(gu, ju[1], gv * jv[1]);
+          gxz = fmaf(gu, ju[2], gv * jv[2]);
+          dldt = dot3(gxx, gxy, gxz, r.dx, r.dy, r.dz);
+        }
+      }
       Pr = fmaf(wk, cr, Pr);
       Pg = fmaf(wk, cg, Pg);
       Pb = fmaf(wk, cb, Pb);
@@ -357,37 +448,41 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
       const float Sb = u.Cb - Pb;
       const float dtau =
           fmaf(u.gb, Tn * cb - Sb, fmaf(u.gg, Tn * cg - Sg, u.gr * (Tn * cr - Sr))) - u.gT * u.Tf;
-      // this cell's record starts with what its entry face already sent it
-      float m_px = c_cell == cur ? c_px : 0.0f;
-      float m_py = c_cell == cur ? c_py : 0.0f;
-      float m_pz = c_cell == cur ? c_pz : 0.0f;
+      // this cell's record starts with what its entry face already sent it,
+      // less the hit point's own pull on the site
+      float m_px = (c_cell == cur ? c_px : 0.0f) - gxx;
+      float m_py = (c_cell == cur ? c_py : 0.0f) - gxy;
+      float m_pz = (c_cell == cur ? c_pz : 0.0f) - gxz;
       int n_cell = -1;
       float n_px = 0.0f, n_py = 0.0f, n_pz = 0.0f;
       if (sg.delta > 0.0f) {
         const float D = c.sigma * dtau;
+        // dL/dt of the entry end (the hit point rides on it when k > 0) and
+        // of the exit end (the start cell's hit point rides on it)
+        const float Din = (k > 0 ? dldt : 0.0f) - D;
+        const float Dex = D + (k == 0 ? dldt : 0.0f);
         if (fa >= 0) {
-          // entry end: -D along the entry face
           if (fa == a_cell) {
-            a_px = fmaf(-D, uax, a_px);
-            a_py = fmaf(-D, uay, a_py);
-            a_pz = fmaf(-D, uaz, a_pz);
+            a_px = fmaf(Din, uax, a_px);
+            a_py = fmaf(Din, uay, a_py);
+            a_pz = fmaf(Din, uaz, a_pz);
           } else if (lead) {
-            atomic_site(g, fa, -D * uax, -D * uay, -D * uaz);
+            atomic_site(g, fa, Din * uax, Din * uay, Din * uaz);
           }
           if (fb == cur) {
-            m_px = fmaf(-D, ubx, m_px);
-            m_py = fmaf(-D, uby, m_py);
-            m_pz = fmaf(-D, ubz, m_pz);
+            m_px = fmaf(Din, ubx, m_px);
+            m_py = fmaf(Din, uby, m_py);
+            m_pz = fmaf(Din, ubz, m_pz);
           } else if (fb == a_cell) {
-            a_px = fmaf(-D, ubx, a_px);
-            a_py = fmaf(-D, uby, a_py);
-            a_pz = fmaf(-D, ubz, a_pz);
+            a_px = fmaf(Din, ubx, a_px);
+            a_py = fmaf(Din, uby, a_py);
+            a_pz = fmaf(Din, ubz, a_pz);
           } else if (lead) {
-            atomic_site(g, fb, -D * ubx, -D * uby, -D * ubz);
+            atomic_site(g, fb, Din * ubx, Din * uby, Din * ubz);
           }
         }
         if (ex.t < r.tmax && ex.next >= 0) {
-          // exit end: +D along the exit face (cur -> next)
+          // exit end: along the exit face (cur -> next)
           const float4 pn = s.cells[2 * (size_t)ex.next];
           const float nx = pn.x - c.px;
           const float ny = pn.y - c.py;
@@ -405,30 +500,50 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
           ubz = (pn.z - xz) * ib;
           fa = cur;
           fb = ex.next;
-          m_px = fmaf(D, uax, m_px);
-          m_py = fmaf(D, uay, m_py);
-          m_pz = fmaf(D, uaz, m_pz);
+          m_px = fmaf(Dex, uax, m_px);
+          m_py = fmaf(Dex, uay, m_py);
+          m_pz = fmaf(Dex, uaz, m_pz);
           n_cell = ex.next;
-          n_px = D * ubx;
-          n_py = D * uby;
-          n_pz = D * ubz;
+          n_px = Dex * ubx;
+          n_py = Dex * uby;
+          n_pz = Dex * ubz;
         }
       }
       // the previous cell is complete: emit it
       if (lead && a_cell >= 0) {
-        e_key = a_cell * RR + tp.base;
+        e_key = (a_cell * MAPS) * RR + a_tp.base;
         e_ds = a_ds;
         e_px = a_px;
         e_py = a_py;
         e_pz = a_pz;
-        e_w = a_w;
+        e_mr = a_mr;
+        e_mg = a_mg;
+        e_mb = a_mb;
+        e_tp = a_tp;
+      }
+      if constexpr (APP == 1) {
+        if (lead) {
+          v_key = (2 * cur + 1) * RR + tp.base;
+          v_mr = glr;
+          v_mg = glg;
+          v_mb = glb;
+        }
       }
       a_cell = cur;
       a_ds = dtau * sg.delta;
       a_px = m_px;
       a_py = m_py;
       a_pz = m_pz;
-      a_w = wk;
+      if constexpr (APP == 0) {
+        a_mr = wk * u.gr;
+        a_mg = wk * u.gg;
+        a_mb = wk * u.gb;
+      } else {
+        a_mr = glr;
+        a_mg = glg;
+        a_mb = glb;
+        a_tp = ts;
+      }
       c_cell = n_cell;
       c_px = n_px;
       c_py = n_py;
@@ -449,13 +564,17 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         cur = ex.next;
       }
     }
-    emit_records<LPR>(e_key, e_ds, e_px, e_py, e_pz, e_w, tp, u, lane, RR, R, g, tab, ob);
+    emit_records<LPR>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane, RR, R, g, tab,
+                      ob);
+    if constexpr (APP == 1)
+      emit_records<LPR>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R, g, tab,
+                        ob);
   }
   // the last visited cell, and the unvisited cell behind an early-stopped ray's exit face
-  emit_records<LPR>(lead && a_cell >= 0 ? a_cell * RR + tp.base : -1, a_ds, a_px, a_py, a_pz, a_w,
-                    tp, u, lane, RR, R, g, tab, ob);
-  emit_records<LPR>(lead && c_cell >= 0 ? c_cell * RR + tp.base : -1, 0.0f, c_px, c_py, c_pz, 0.0f,
-                    tp, u, lane, RR, R, g, tab, ob);
+  emit_records<LPR>(lead && a_cell >= 0 ? (a_cell * MAPS) * RR + a_tp.base : -1, a_ds, a_px, a_py,
+                    a_pz, a_tp, a_mr, a_mg, a_mb, lane, RR, R, g, tab, ob);
+  emit_records<LPR>(lead && c_cell >= 0 ? (c_cell * MAPS) * RR + tp.base : -1, 0.0f, c_px, c_py,
+                    c_pz, tp, 0.0f, 0.0f, 0.0f, lane, RR, R, g, tab, ob);
 }
 
 }  // namespace voro

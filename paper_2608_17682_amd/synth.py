@@ -317,6 +317,19 @@ def scene_from_arrays(sites, density, texels, with_csr=True, name="custom") -> S
                  np.ascontiguousarray(texels, np.float32), off, idx, name=name)
 
 
+def full_texels(n: int, res: int, seed: int, vi_scale: float = 1.5,
+                vd_scale: float = 0.5) -> np.ndarray:
+    """Seeded logits for the two-map appearance model, [n, 2, res, res, 4] f32:
+    surface map N(0, vi_scale^2), view map a smaller residual N(0, vd_scale^2),
+    A channel zero (Sec. 5.1, 5.2; the paper starts the view map at zero and
+    keeps it small with a regulariser)."""
+    rng = np.random.default_rng(5000 + seed)
+    tex = np.zeros((n, 2, res, res, 4), np.float32)
+    tex[:, 0, :, :, :3] = rng.normal(0.0, vi_scale, (n, res, res, 3))
+    tex[:, 1, :, :, :3] = rng.normal(0.0, vd_scale, (n, res, res, 3))
+    return tex
+
+
 def texels_rgb(n: int, res: int, rgb) -> np.ndarray:
     tex = np.zeros((n, res, res, 4), np.float32)
     tex[..., :3] = np.asarray(rgb, np.float32)

@@ -52,7 +52,7 @@ class VoroError(RuntimeError):
 
 class voro_scene(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int32), ("tex_res", ctypes.c_int32),
-                ("tex_dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("tex_dtype", ctypes.c_int32), ("tex_maps", ctypes.c_int32),
                 ("n_edges", ctypes.c_int64), ("sites", ctypes.c_void_p),
                 ("density", ctypes.c_void_p), ("nbr_off", ctypes.c_void_p),
                 ("nbr_idx", ctypes.c_void_p), ("texels", ctypes.c_void_p)]
@@ -209,7 +209,9 @@ class DeviceScene:
     """The scene's device arrays plus its prepared workspace.
 
     sites [N,3] f32, density [N] f32, nbr_off [N+1] i32, nbr_idx [M] i32,
-    texels [N,R,R,4] f32/f16/bf16 - all contiguous device tensors.
+    texels [N,R,R,4] f32/f16/bf16 - all contiguous device tensors; texels
+    [N,2,R,R,4] hold the surface and view maps of the full appearance model
+    (params.appearance = 1).
     """
 
     def __init__(self, sites, density, nbr_off, nbr_idx, texels):
@@ -234,14 +236,22 @@ class DeviceScene:
 
     @property
     def tex_res(self):
-        return int(self.texels.shape[1])
+        return int(self.texels.shape[-2])
+
+    @property
+    def tex_maps(self):
+        if self.texels.dim() == 5:
+            if int(self.texels.shape[1]) != 2:
+                raise ValueError("texels [N,2,R,R,4] expected for two maps")
+            return 2
+        return 1
 
     def c(self) -> voro_scene:
         s = voro_scene()
         s.n_sites = self.n
         s.tex_res = self.tex_res
         s.tex_dtype = self.tex_dtype
-        s.reserved0 = 0
+        s.tex_maps = self.tex_maps
         s.n_edges = int(self.nbr_idx.shape[0])
         s.sites = _ptr(self.sites)
         s.density = _ptr(self.density)

@@ -71,7 +71,7 @@ def test_version_and_defaults(L):
 
 def fake_scene(n=10, m=40, res=4, dtype=0, addr=0x100000):
     s = voro.voro_scene()
-    s.n_sites, s.tex_res, s.tex_dtype, s.reserved0, s.n_edges = n, res, dtype, 0, m
+    s.n_sites, s.tex_res, s.tex_dtype, s.tex_maps, s.n_edges = n, res, dtype, 0, m
     s.sites, s.density, s.nbr_off, s.nbr_idx, s.texels = addr, addr, addr, addr, addr
     return s
 
@@ -84,7 +84,7 @@ def test_workspace_size_host_only(L):
 
 
 @pytest.mark.parametrize("field,value", [("n_sites", 0), ("tex_res", 1), ("tex_res", 17),
-                                         ("tex_dtype", 7), ("n_edges", -1), ("reserved0", 1)])
+                                         ("tex_dtype", 7), ("n_edges", -1), ("tex_maps", 3)])
 def test_bad_scene_is_einval(L, field, value):
     s = fake_scene()
     setattr(s, field, value)
@@ -117,14 +117,27 @@ def test_render_validation_before_device(L):
     assert st == voro.VORO_EINVAL
     # bad params
     for field, value in [("max_steps", 0), ("lanes_per_ray", 3), ("block", 100),
-                         ("t_stop", float("nan")), ("appearance", 1)]:
+                         ("t_stop", float("nan")), ("appearance", 1), ("appearance", 2)]:
         q = voro.default_params(**{field: value})
         st = L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
                                None, None, None, None)
         assert st in (voro.VORO_EINVAL, voro.VORO_EUNSUPPORTED), field
-    q = voro.default_params(appearance=1)
+    q = voro.default_params(appearance=2)
     assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
                              None, None, None, None) == voro.VORO_EUNSUPPORTED
+    # the full appearance model needs two maps per cell, and the single-map
+    # model one
+    q = voro.default_params(appearance=1)
+    assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
+                             None, None, None, None) == voro.VORO_EINVAL
+    assert "two texture maps" in voro.last_error()
+    s2 = voro.voro_scene.from_buffer_copy(s)
+    s2.tex_maps = 2
+    n2 = ctypes.c_size_t()
+    assert L.voro_workspace_size(ctypes.byref(s2), ctypes.byref(n2)) == 0
+    assert L.voro_render_fwd(ctypes.byref(s2), ws, n2.value, A, A, A, A, 8, ctypes.byref(p), A, A,
+                             None, None, None, None) == voro.VORO_EINVAL
+    assert "one texture map" in voro.last_error()
     q = voro.default_params(tile_w=8, tile_h=4)  # 8*4*1 != 64
     assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
                              None, None, None, None) == voro.VORO_EINVAL
