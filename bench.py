@@ -367,6 +367,41 @@ def main():
         s = timed(fb, max(2, args.steps // 2), 1)
         extras["fwd_bwd_f32_mrays_s"] = round(rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
         del gs, gd, gt
+        # the paper's full appearance model (Sec. 5.1/5.2): surface + view maps
+        # of seeded logits, same scene, walk and launches
+        full = torch.from_numpy(synth.full_texels(scene.n, scene.tex_res, seed=2)).to(dev)
+        if not args.no_morton:
+            full = full[perm.long()].contiguous()
+        dsf = ds.with_arrays(texels=full)
+        voro.voro_prepare(dsf)
+
+        def with_app(p):
+            q = voro.voro_params.from_buffer_copy(p)
+            q.appearance = 1
+            return q
+        pf, pfb = with_app(params), with_app(params_bwd)
+        fa = {}
+        s = timed(lambda: step(dsf, pf), args.steps, args.warmup)
+        fa["fwd_f32_mrays_s"] = round(rays_per_step * args.steps / s / 1e6, 2)
+        dsf16 = dsf.with_arrays(texels=voro.voro_cast_texels(full, "float16"))
+        voro.voro_prepare(dsf16)
+        s = timed(lambda: step(dsf16, pf), args.steps, args.warmup)
+        fa["fwd_float16_mrays_s"] = round(rays_per_step * args.steps / s / 1e6, 2)
+        del dsf16
+        gs = torch.zeros((ds.n, 3), device=dev)
+        gd = torch.zeros(ds.n, device=dev)
+        gt = torch.zeros(tuple(full.shape), device=dev)
+
+        def fbf():
+            voro.voro_prepare(dsf)
+            for i in range(N_POSES):
+                frame(i, pf, dsf)
+                voro.voro_render_views_bwd(dsf, [ccams[i]], rgb, T, None, g_rgb, None, pfb,
+                                           gs, gd, gt)
+        s = timed(fbf, max(2, args.steps // 2), 1)
+        fa["fwd_bwd_f32_mrays_s"] = round(rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
+        extras["full_appearance"] = fa
+        del gs, gd, gt, dsf, full
         log(f"extras: {extras}")
         for name, fn in (("config3", bench_config3), ("config5", bench_config5)):
             if name not in large:
