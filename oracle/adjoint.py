@@ -36,12 +36,19 @@ d = (x - p_i)/r, r = |x - p_i|, the hit point x = o + t_hit w gives
     dL/dx = (I - d d^T) dL/dd / r,   dL/dp_i -= dL/dx,   dL/dt_hit = dL/dx . w,
 and t_hit moves with the crossing that defines it (the entry face, or the
 start cell's exit face), through the same dt/dp as above.
+
+Distortion loss (Sec. 5.3), L += g_dist L_dist, with G_k = dL_dist/dw_k and
+the interval-end partials from ``distortion.distortion_partials``: since
+w_k = T_k - T_{k+1} and T_k = exp(-sum_{j<k} tau_j),
+    dL_dist/dtau_j = G_j T_{j+1} - sum_{k>j} G_k w_k,
+and the interval ends t_k (entry) and t_k + delta_k (exit, unless clipped
+at tmax) move with their crossings like the segment ends above.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import appearance, walk
+from . import appearance, distortion, walk
 
 
 def face_dt_dsites(sites, a, b, o, w, t):
@@ -56,8 +63,9 @@ def face_dt_dsites(sites, a, b, o, w, t):
 
 
 def grad_ray(sites, density, texels, o, w, tmax, rec, g_rgb, g_T, g_sites, g_density,
-             g_texels):
-    """Accumulate dL/d(sites, density, texels) of one ray into the dense arrays.
+             g_texels, g_dist=0.0):
+    """Accumulate dL/d(sites, density, texels) of one ray into the dense arrays, for
+    L = g_rgb . C + g_T T_final + g_dist L_dist.
 
     ``rec`` is the oracle forward record of this ray (render.render_ray).
     """
@@ -77,6 +85,16 @@ def grad_ray(sites, density, texels, o, w, tmax, rec, g_rgb, g_T, g_sites, g_den
         taps = appearance.bilinear_weights(w, res)
     p64 = walk.as64(sites)
     o64 = walk.as64(o)
+    gdist = float(g_dist)
+    if gdist != 0.0:
+        t_ends = [a + b for a, b in zip(rec.t_in, rec.delta)]
+        Gw, Gt0, Gt1 = distortion.distortion_partials(rec.weight, rec.t_in, t_ends)
+        Gw_suffix = np.zeros(K + 1)          # sum_{k>=j} G_k w_k
+        for k in range(K - 1, -1, -1):
+            Gw_suffix[k] = Gw_suffix[k + 1] + Gw[k] * rec.weight[k]
+    else:
+        Gw = Gt0 = Gt1 = np.zeros(K)
+        Gw_suffix = np.zeros(K + 1)
     # suffix sums S_k = C - sum_{j<=k} w_j c_j
     prefix = np.zeros(3)
     entry_face = None  # (a, b, t) of the crossing that set the current entry
@@ -88,6 +106,7 @@ def grad_ray(sites, density, texels, o, w, tmax, rec, g_rgb, g_T, g_sites, g_den
         S = C - prefix
         T_next = rec.T_before[k] * np.exp(-sig[i] * rec.delta[k])
         dtau = float(g @ (T_next * ck - S)) - gT * Tf
+        dtau += gdist * (Gw[k] * T_next - Gw_suffix[k + 1])
         g_density[i] += dtau * rec.delta[k]
         if not rec.skipped[k] and app == 0:
             for r, col, bw in taps:
@@ -124,17 +143,19 @@ def grad_ray(sites, density, texels, o, w, tmax, rec, g_rgb, g_T, g_sites, g_den
             if entry_face is not None:
                 a, b, t = entry_face
                 da, db = face_dt_dsites(sites, a, b, o, w, t)
-                g_sites[a] -= ddelta * da
-                g_sites[b] -= ddelta * db
+                c_in = gdist * Gt0[k] - ddelta
+                g_sites[a] += c_in * da
+                g_sites[b] += c_in * db
             ex = rec.exit[k]
             if ex < tmax and rec.nxt[k] >= 0:
                 da, db = face_dt_dsites(sites, i, rec.nxt[k], o, w, ex)
-                g_sites[i] += ddelta * da
-                g_sites[rec.nxt[k]] += ddelta * db
+                c_out = ddelta + gdist * Gt1[k]
+                g_sites[i] += c_out * da
+                g_sites[rec.nxt[k]] += c_out * db
                 entry_face = (i, rec.nxt[k], ex)
 
 
-def grad_rays(sites, density, texels, origins, dirs, tmax, recs, g_rgb, g_T):
+def grad_rays(sites, density, texels, origins, dirs, tmax, recs, g_rgb, g_T, g_dist=None):
     """Dense FP64 gradients summed over rays: (g_sites[N,3], g_density[N], g_texels
     shaped like texels: [N,R,R,4], or [N,2,R,R,4] for the full appearance model)."""
     N = len(sites)
@@ -146,5 +167,5 @@ def grad_rays(sites, density, texels, origins, dirs, tmax, recs, g_rgb, g_T):
         if rec is None:
             continue
         grad_ray(sites, density, texels, origins[r], dirs[r], tm[r], rec, g_rgb[r], g_T[r],
-                 gs, gd, gt)
+                 gs, gd, gt, 0.0 if g_dist is None else g_dist[r])
     return gs, gd, gt

@@ -25,6 +25,8 @@ the ray's origin.  Readings of what the paper leaves open:
   composites every segment;
 * rays cover t in [0, tmax] with no near plane and no background colour
   (the returned colour is premultiplied).
+The record also carries the ray's distortion loss (Sec. 5.3) over the
+segments [t_k, t_k + delta_k] with their weights w_k.
 """
 from __future__ import annotations
 
@@ -34,7 +36,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import appearance as appearance_mod, walk
+from . import appearance as appearance_mod, distortion, walk
 
 
 @dataclasses.dataclass
@@ -55,6 +57,7 @@ class RayRecord:
     stop: str                # "tstop" | "tmax" | "max_steps"
     start_gap: float = math.inf
     appearance: int = 0
+    dist: float = 0.0        # distortion loss of the ray (Sec. 5.3)
     t_hit: List[float] = dataclasses.field(default_factory=list)    # appearance 1
     surf_dir: List[np.ndarray] = dataclasses.field(default_factory=list)
 
@@ -147,6 +150,8 @@ def render_ray(sites, density, texels, o, w, tmax, t_stop=1e-4, skip_w=0.0,
             break
     rec.rgb = C
     rec.T = T
+    rec.dist = distortion.distortion(rec.weight, rec.t_in,
+                                     [a + b for a, b in zip(rec.t_in, rec.delta)])
     return rec
 
 
