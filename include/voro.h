@@ -253,17 +253,22 @@ voro_status voro_locate_origins(const voro_scene* scene, const void* ws, size_t 
  *   nsteps [R] int32 out or NULL: cells visited K(r)
  *   cells [R, params.max_record] int32 out or NULL: the first max_record
  *         visited cells per ray, -1 padded
+ *   dist [R,3] float out or NULL: the ray's distortion loss (Sec. 5.3,
+ *         eq. distortion-loss) sum_{k,l} w_k w_l |sbar_k - sbar_l| +
+ *         1/3 sum_k w_k^2 ds_k over its segments, s(t) = 1 - 1/(1+t), then
+ *         sum_k w_k sbar_k and sum_k w_k (kept for voro_render_bwd)
  * Rays with tmax <= 0 return rgb = 0, T = 1, K = 0.  Start cells out of
  * range return rgb = 0, T = 1 and are counted.  Requires voro_prepare.
  */
 voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_bytes,
                             const float* o, const float* d, const float* tmax,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
-                            float* rgb, float* T, int32_t* nsteps, int32_t* cells,
+                            float* rgb, float* T, int32_t* nsteps, int32_t* cells, float* dist,
                             uint64_t* stats, void* stream);
 
 /*
- * Adjoint of voro_render_fwd for L = sum_r g_rgb[r].rgb[r] + g_T[r] T[r].
+ * Adjoint of voro_render_fwd for L = sum_r g_rgb[r].rgb[r] + g_T[r] T[r]
+ * (+ g_dist[r] L_dist[r]).
  * Replays each ray's walk (same code, same cell sequence) and recovers the
  * back-to-front colour suffix from the saved forward totals rgb and T, so
  * nothing per step is stored between the passes.  Accumulates (+=, FP32
@@ -271,7 +276,9 @@ voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_b
  *   g_sites [N,3], g_density [N] (dL/dsigma), g_texels [N,R,R,4] float
  *   ([N,2,R,R,4] with tex_maps = 2; A channel untouched), whatever the
  *   texel storage type.
- * g_T may be NULL (zero).  params.skip_w must be 0.  Gradients reach site
+ * g_T may be NULL (zero).  dist [R,3] (voro_render_fwd's output) and g_dist
+ * [R] add L += sum_r g_dist[r] dist[r,0]; both NULL or both given.
+ * params.skip_w must be 0.  Gradients reach site
  * positions through the crossing parameters of the bisector faces and, with
  * appearance 1, through the surface direction x - p_i (x moving with the
  * crossing that places it); tmax, early termination and max_steps pass none.
@@ -280,8 +287,9 @@ voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_b
                             const float* o, const float* d, const float* tmax,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
                             const float* rgb, const float* T, const float* g_rgb,
-                            const float* g_T, float* g_sites, float* g_density,
-                            float* g_texels, uint64_t* stats, void* stream);
+                            const float* g_T, const float* dist, const float* g_dist,
+                            float* g_sites, float* g_density, float* g_texels, uint64_t* stats,
+                            void* stream);
 
 /* ------------------------------------------------------------ cameras */
 

@@ -1,7 +1,8 @@
 """torch.autograd.Functions over the HIP renderer.
 
 ``render(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start)``
-returns (rgb [R,3], T [R]) for explicit rays; ``render_views(sites, density,
+returns (rgb [R,3], T [R]) for explicit rays (and, with distortion=True,
+each ray's distortion loss of Sec. 5.3); ``render_views(sites, density,
 texels, nbr_off, nbr_idx, cameras)`` returns per-pixel (rgb [P,3], T [P])
 for up to 16 cameras generated in-kernel (one launch each way).  Both are
 differentiable with respect to the site positions, the densities sigma and
@@ -19,29 +20,40 @@ from . import voro
 
 class VoroRender(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params):
+    def forward(ctx, sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params,
+                with_dist):
         ds = voro.DeviceScene(sites.detach().contiguous(), density.detach().contiguous(),
                               nbr_off, nbr_idx, texels.detach().contiguous())
         voro.voro_prepare(ds)
-        rgb, T = voro.voro_render_fwd(ds, o, d, tmax, start, params)
+        dist = (torch.empty((o.shape[0], 3), dtype=torch.float32, device=o.device)
+                if with_dist else None)
+        rgb, T = voro.voro_render_fwd(ds, o, d, tmax, start, params, dist=dist)
         ctx.ds = ds
         ctx.params = params
         ctx.tex_dtype = texels.dtype
-        ctx.save_for_backward(o, d, tmax, start, rgb, T)
+        ctx.with_dist = with_dist
+        ctx.save_for_backward(o, d, tmax, start, rgb, T,
+                              dist if with_dist else torch.empty(0, device=o.device))
+        if with_dist:
+            return rgb, T, dist[:, 0]
         return rgb, T
 
     @staticmethod
-    def backward(ctx, g_rgb, g_T):
-        o, d, tmax, start, rgb, T = ctx.saved_tensors
+    def backward(ctx, g_rgb, g_T, g_dist=None):
+        o, d, tmax, start, rgb, T, dist = ctx.saved_tensors
         ds = ctx.ds
         if g_rgb is None:
             g_rgb = torch.zeros_like(rgb)
+        if ctx.with_dist and g_dist is not None:
+            dist_in, g_dist = dist, g_dist.contiguous()
+        else:
+            dist_in, g_dist = None, None
         gs, gd, gt = voro.voro_render_bwd(
             ds, o, d, tmax, start, rgb, T, g_rgb.contiguous(),
-            None if g_T is None else g_T.contiguous(), ctx.params)
+            None if g_T is None else g_T.contiguous(), ctx.params, dist=dist_in, g_dist=g_dist)
         if ctx.tex_dtype != torch.float32:
             gt = gt.to(ctx.tex_dtype)
-        return gs, gd, gt, None, None, None, None, None, None, None
+        return gs, gd, gt, None, None, None, None, None, None, None, None
 
 
 class VoroRenderViews(torch.autograd.Function):
@@ -86,11 +98,15 @@ def render_views(sites, density, texels, nbr_off, nbr_idx, cams, params_fwd=None
                                  params_bwd)
 
 
-def render(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params=None):
-    """Differentiable render of explicit rays; see the module docstring."""
+def render(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params=None,
+           distortion=False):
+    """Differentiable render of explicit rays; see the module docstring.  With
+    distortion=True also returns each ray's distortion loss (Sec. 5.3), [R],
+    differentiable like the colour."""
     if params is None:
         params = voro.default_params()
     if params.skip_w != 0.0 and torch.is_grad_enabled() and (
             sites.requires_grad or density.requires_grad or texels.requires_grad):
         raise ValueError("skip_w must be 0 when gradients are needed")
-    return VoroRender.apply(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params)
+    return VoroRender.apply(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params,
+                            bool(distortion))

@@ -93,11 +93,14 @@ struct RayArgs {
   int32_t* nsteps;
   int32_t* cells_out;
   int max_record;
+  float* dist_out;  // [R,3] distortion loss, sum w sbar, sum w (or null)
   // backward inputs / outputs
   const float* rgb_in;
   const float* T_in;
   const float* g_rgb;
   const float* g_T;
+  const float* dist_in;  // [R,3] saved by the forward (with g_dist)
+  const float* g_dist;   // [R] upstream gradient of the distortion loss (or null)
   Grads g;
   unsigned long long* stats;
 };
@@ -124,13 +127,19 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
     r.start = a.start[ray];
     int32_t* rec = (a.cells_out && a.max_record > 0) ? a.cells_out + (size_t)ray * a.max_record
                                                      : nullptr;
-    const RayOut out = walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, rec, a.max_record, cnt);
+    const RayOut out =
+        walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, rec, a.max_record, cnt, a.dist_out != nullptr);
     if (sub == 0) {
       a.rgb[3 * (size_t)ray] = out.r;
       a.rgb[3 * (size_t)ray + 1] = out.g;
       a.rgb[3 * (size_t)ray + 2] = out.b;
       a.T[ray] = out.T;
       if (a.nsteps) a.nsteps[ray] = out.k;
+      if (a.dist_out) {
+        a.dist_out[3 * (size_t)ray] = out.dist;
+        a.dist_out[3 * (size_t)ray + 1] = out.dist_a;
+        a.dist_out[3 * (size_t)ray + 2] = out.dist_w;
+      }
       if (rec)
         for (int k = out.k; k < a.max_record; ++k) rec[k] = -1;
     }
@@ -167,6 +176,12 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
     u.gg = a.g_rgb[3 * (size_t)ray + 1];
     u.gb = a.g_rgb[3 * (size_t)ray + 2];
     u.gT = a.g_T ? a.g_T[ray] : 0.0f;
+    if (a.g_dist) {
+      u.D = a.dist_in[3 * (size_t)ray];
+      u.DA = a.dist_in[3 * (size_t)ray + 1];
+      u.DW = a.dist_in[3 * (size_t)ray + 2];
+      u.gD = a.g_dist[ray];
+    }
   }
   __shared__ int s_keys[kTableCap];
   __shared__ float s_vals[16 * kTableCap];
@@ -180,7 +195,8 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
   __syncthreads();
   // all lanes take part: the gradient records are merged across the wave,
   // then across the workgroup in the LDS table
-  walk_backward<LPR, TEX, APP>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, ob, cnt);
+  walk_backward<LPR, TEX, APP>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, ob, cnt,
+                               a.g_dist != nullptr);
   __syncthreads();
   table_flush(tab, a.g, a.s.res * a.s.res, a.s.res);
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
@@ -323,7 +339,7 @@ voro_status voro_prepare(const voro_scene* scene, void* ws, size_t ws_bytes, uin
 voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_bytes,
                             const float* o, const float* d, const float* tmax,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
-                            float* rgb, float* T, int32_t* nsteps, int32_t* cells,
+                            float* rgb, float* T, int32_t* nsteps, int32_t* cells, float* dist,
                             uint64_t* stats, void* stream) {
   if (R > 0 && (!rgb || !T)) return fail(VORO_EINVAL, "rgb and T must not be NULL");
   if (params && params->max_record > 0 && !cells)
@@ -334,6 +350,7 @@ voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_b
   a.nsteps = nsteps;
   a.cells_out = cells;
   a.max_record = params ? params->max_record : 0;
+  a.dist_out = dist;
   a.stats = reinterpret_cast<unsigned long long*>(stats);
   return ray_launch(false, scene, ws, ws_bytes, o, d, tmax, start_cell, R, params, a, stream);
 }
@@ -342,10 +359,13 @@ voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_b
                             const float* o, const float* d, const float* tmax,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
                             const float* rgb, const float* T, const float* g_rgb,
-                            const float* g_T, float* g_sites, float* g_density,
-                            float* g_texels, uint64_t* stats, void* stream) {
+                            const float* g_T, const float* dist, const float* g_dist,
+                            float* g_sites, float* g_density, float* g_texels, uint64_t* stats,
+                            void* stream) {
   if (R > 0 && (!rgb || !T || !g_rgb))
     return fail(VORO_EINVAL, "rgb, T and g_rgb must not be NULL");
+  if ((dist == nullptr) != (g_dist == nullptr))
+    return fail(VORO_EINVAL, "dist and g_dist must both be given or both be NULL");
   if (R > 0 && (!g_sites || !g_density || !g_texels))
     return fail(VORO_EINVAL, "gradient outputs must not be NULL");
   if (g_texels && !aligned(g_texels, 16)) return fail(VORO_EINVAL, "g_texels must be 16-byte aligned");
@@ -354,6 +374,8 @@ voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_b
   a.T_in = T;
   a.g_rgb = g_rgb;
   a.g_T = g_T;
+  a.dist_in = dist;
+  a.g_dist = g_dist;
   a.g.sites = g_sites;
   a.g.density = g_density;
   a.g.texels = g_texels;

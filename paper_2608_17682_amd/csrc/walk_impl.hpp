@@ -27,13 +27,23 @@ struct RayIn {
 struct RayOut {
   float r, g, b, T;
   int k;
+  float dist, dist_a, dist_w;  // distortion loss and its running totals (when asked for)
 };
 
-// saved forward totals and upstream gradient of one ray
+// saved forward totals and upstream gradient of one ray; with the
+// distortion loss also its saved value and totals sum w sbar, sum w, and
+// its upstream gradient
 struct Upstream {
   float Cr, Cg, Cb, Tf;
   float gr, gg, gb, gT;
+  float D, DA, DW, gD;
 };
+
+// Distortion loss (Sec. 5.3): s(t) = t / (1 + t) maps depth into [0, 1).
+// Along a ray the intervals are ordered, so the pair sum runs on prefix
+// sums: segment k adds 2 w_k (sbar_k W - A) + w_k^2 ds_k / 3, with W, A the
+// sums of w and w sbar over the earlier segments.
+__device__ __forceinline__ float dist_s(float t) { return t / (1.0f + t); }
 
 struct Grads {
   float* sites;    // [N,3]
@@ -96,11 +106,13 @@ __device__ __forceinline__ Taps ray_taps(const RayIn& r, int R) {
 template <int LPR, int TEX, int APP>
 __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkParams& w,
                                                const RayIn& r, int sub, int32_t* rec,
-                                               int max_record, Counters& cnt) {
+                                               int max_record, Counters& cnt,
+                                               bool dist_on = false) {
   RayOut out;
   out.r = out.g = out.b = 0.0f;
   out.T = 1.0f;
   out.k = 0;
+  out.dist = out.dist_a = out.dist_w = 0.0f;
   if (!(r.tmax > 0.0f)) return out;
   if (r.start < 0 || r.start >= s.n) {
     cnt.bad++;
@@ -109,6 +121,7 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
   cnt.rays++;
   const Taps tp = ray_taps<APP>(r, s.res);
   float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, t_in = 0.0f;
+  float dP = 0.0f, dQ = 0.0f, dW = 0.0f, dA = 0.0f, s0 = 0.0f;
   int cur = r.start;
   int k = 0;
   for (;;) {
@@ -118,6 +131,15 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
     cnt.deg += (uint32_t)c.deg;
     const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
     const float wk = T * sg.alpha;
+    if (dist_on) {
+      const float s1 = dist_s(fmaxf(t_in, fminf(ex.t, r.tmax)));
+      const float sb = 0.5f * (s0 + s1);
+      dP = fmaf(2.0f * wk, fmaf(sb, dW, -dA), dP);
+      dQ = fmaf(wk * wk, s1 - s0, dQ);
+      dW += wk;
+      dA = fmaf(wk, sb, dA);
+      s0 = s1;
+    }
     if (wk >= w.skip_w) {
       float cr, cg, cb;
       if constexpr (APP == 0) {
@@ -160,6 +182,9 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
   out.b = Cb;
   out.T = T;
   out.k = k;
+  out.dist = fmaf(dQ, 1.0f / 3.0f, dP);
+  out.dist_a = dA;
+  out.dist_w = dW;
   return out;
 }
 
@@ -352,11 +377,18 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
 // octahedral map's Jacobian at x - p_i: -dL/dx goes to the site, and
 // dL/dt_hit = dL/dx . w to the crossing that placed x (the entry face, or
 // the start cell's exit face) through the same dt/dp as the segment ends.
+//
+// Distortion loss (dist_on): with G_k = dL_dist/dw_k, the chain through
+// w_k = T_k - T_{k+1} gives dL_dist/dtau_k = G_k T_{k+1} - sum_{j>k} G_j w_j,
+// and sum_j G_j w_j = 2 L_dist, so the suffix follows from the saved loss;
+// the interval ends move with their crossings through
+// dL_dist/dt = (dL/dsbar / 2 -+ dL/dds) s'(t), s'(t) = 1/(1+t)^2.
 template <int LPR, int TEX, int APP>
 __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParams& w, const RayIn& r,
                                               const Upstream& u, bool has_ray, int sub, int lane,
                                               const Grads& g, const GradTable* tab,
-                                              const Outbox& ob, Counters& cnt) {
+                                              const Outbox& ob, Counters& cnt,
+                                              bool dist_on = false) {
   const int R = s.res;
   const int RR = R * R;
   constexpr int MAPS = APP ? 2 : 1;
@@ -369,6 +401,7 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
   const bool lead = sub == 0;
   const Taps tp = ray_taps<APP>(r, R);
   float T = 1.0f, Pr = 0.0f, Pg = 0.0f, Pb = 0.0f, t_in = 0.0f;
+  float dW = 0.0f, dA = 0.0f, dGW = 0.0f, s0 = 0.0f;  // distortion prefix sums
   int cur = active ? r.start : 0;
   int k = 0;
   // previous cell's record (emitted one step late): its texel multipliers
@@ -446,8 +479,31 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
       const float Sr = u.Cr - Pr;
       const float Sg = u.Cg - Pg;
       const float Sb = u.Cb - Pb;
-      const float dtau =
+      float dtau =
           fmaf(u.gb, Tn * cb - Sb, fmaf(u.gg, Tn * cg - Sg, u.gr * (Tn * cr - Sr))) - u.gT * u.Tf;
+      float dist_in = 0.0f, dist_ex = 0.0f;  // dL_dist/dt of the interval's ends
+      if (dist_on) {
+        const float t1 = fmaxf(t_in, fminf(ex.t, r.tmax));
+        const float s1 = dist_s(t1);
+        const float sb = 0.5f * (s0 + s1);
+        const float dsv = s1 - s0;
+        const float Wle = dW + wk;
+        const float Ale = fmaf(wk, sb, dA);
+        const float Gk = 2.0f * (fmaf(sb, dW, -dA) + (u.DA - Ale) - sb * (u.DW - Wle)) +
+                         (2.0f / 3.0f) * wk * dsv;
+        const float GWle = fmaf(Gk, wk, dGW);
+        dtau = fmaf(u.gD, fmaf(Gk, Tn, -(2.0f * u.D - GWle)), dtau);
+        const float gsb = 2.0f * wk * (dW - (u.DW - Wle));
+        const float gds = wk * wk * (1.0f / 3.0f);
+        const float i0 = 1.0f / (1.0f + t_in);
+        const float i1 = 1.0f / (1.0f + t1);
+        dist_in = u.gD * fmaf(0.5f, gsb, -gds) * (i0 * i0);
+        dist_ex = u.gD * fmaf(0.5f, gsb, gds) * (i1 * i1);
+        dW = Wle;
+        dA = Ale;
+        dGW = GWle;
+        s0 = s1;
+      }
       // this cell's record starts with what its entry face already sent it,
       // less the hit point's own pull on the site
       float m_px = (c_cell == cur ? c_px : 0.0f) - gxx;
@@ -459,8 +515,8 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         const float D = c.sigma * dtau;
         // dL/dt of the entry end (the hit point rides on it when k > 0) and
         // of the exit end (the start cell's hit point rides on it)
-        const float Din = (k > 0 ? dldt : 0.0f) - D;
-        const float Dex = D + (k == 0 ? dldt : 0.0f);
+        const float Din = (k > 0 ? dldt : 0.0f) - D + dist_in;
+        const float Dex = D + (k == 0 ? dldt : 0.0f) + dist_ex;
         if (fa >= 0) {
           if (fa == a_cell) {
             a_px = fmaf(Din, uax, a_px);

@@ -103,6 +103,28 @@ def test_full_bwd_matches_oracle_gradient(dev, cf, lpr):
     assert np.abs(want[2][:, 0]).max() > 0 and np.abs(want[2][:, 1]).max() > 0
 
 
+def test_full_model_with_distortion(dev, cf):
+    deg = np.array([degenerate(r, 1e-4, float(cf.tm[0])) for r in cf.recs])
+    sel = np.nonzero(~deg)[0][::2]
+    g_rgb, g_T = synth.upstream(len(cf.o), 2)
+    g_rgb, g_T = g_rgb[sel], g_T[sel]
+    g_dist = np.random.default_rng(3).normal(0.0, 2.0, len(sel)).astype(np.float32)
+    want = adjoint.grad_rays(cf.scene.sites, cf.scene.density, cf.tex, cf.o[sel], cf.d[sel],
+                             cf.tm[sel], [cf.recs[i] for i in sel], g_rgb, g_T, g_dist)
+    announce("full appearance + distortion bwd")
+    p = voro.default_params(appearance=1)
+    si = torch.from_numpy(sel).to(dev)
+    dist = torch.empty((len(sel), 3), dtype=torch.float32, device=dev)
+    rgb, T = voro.voro_render_fwd(cf.ds, cf.O[si], cf.D[si], cf.TM[si], cf.S[si], p, dist=dist)
+    np.testing.assert_allclose(dist[:, 0].cpu().numpy(), [cf.recs[i].dist for i in sel],
+                               atol=2e-6, rtol=1e-4)
+    got = voro.voro_render_bwd(cf.ds, cf.O[si], cf.D[si], cf.TM[si], cf.S[si], rgb, T,
+                               to_dev(g_rgb, dev), to_dev(g_T, dev), p, dist=dist,
+                               g_dist=to_dev(g_dist, dev))
+    for g, w, name in zip(got, want, ("sites", "density", "texels")):
+        assert_grad_close(g.cpu().numpy(), w, name)
+
+
 def test_full_views_equal_explicit(dev, cf):
     cams = synth.config5_cameras(scale=0.05)
     for cm in cams:

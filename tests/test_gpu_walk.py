@@ -345,6 +345,67 @@ def test_views_bwd_equals_explicit(dev, c1):
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), name
 
 
+def test_distortion_fwd_matches_oracle(dev, c1):
+    R = len(c1.o)
+    dist = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    announce("distortion loss fwd config1")
+    rgb, T = voro.voro_render_fwd(c1.ds, c1.O, c1.D, c1.TM, c1.S, voro.default_params(),
+                                  dist=dist)
+    dist = dist.cpu().numpy()
+    keep = np.array([not stop_degenerate(r, 1e-4) for r in c1.recs])
+    want = np.array([r.dist for r in c1.recs])
+    wsum = np.array([sum(r.weight) for r in c1.recs])
+    assert want.max() > 0.01
+    np.testing.assert_allclose(dist[keep, 0], want[keep], atol=2e-6, rtol=1e-4)
+    np.testing.assert_allclose(dist[keep, 2], wsum[keep], atol=1e-5, rtol=0)
+    # the colour is unchanged by asking for the loss
+    rgb0, _ = voro.voro_render_fwd(c1.ds, c1.O, c1.D, c1.TM, c1.S, voro.default_params())
+    assert torch.equal(rgb, rgb0)
+
+
+@pytest.mark.parametrize("lpr", [1, 4])
+def test_distortion_bwd_matches_oracle_gradient(dev, c1, lpr):
+    deg = np.array([degenerate(r, 1e-4, float(c1.tm[0])) for r in c1.recs])
+    sel = np.nonzero(~deg)[0]
+    g_rgb, g_T = synth.upstream(len(c1.o), 1)
+    g_rgb, g_T = g_rgb[sel], g_T[sel]
+    g_dist = np.random.default_rng(17).normal(0.0, 3.0, len(sel)).astype(np.float32)
+    want = adjoint.grad_rays(c1.scene.sites, c1.scene.density, c1.scene.texels, c1.o[sel],
+                             c1.d[sel], c1.tm[sel], [c1.recs[i] for i in sel], g_rgb, g_T, g_dist)
+    announce(f"distortion bwd config1 lpr={lpr}")
+    si = torch.from_numpy(sel).to(dev)
+    p = voro.default_params(lanes_per_ray=lpr)
+    dist = torch.empty((len(sel), 3), dtype=torch.float32, device=dev)
+    rgb, T = voro.voro_render_fwd(c1.ds, c1.O[si], c1.D[si], c1.TM[si], c1.S[si], p, dist=dist)
+    got = voro.voro_render_bwd(c1.ds, c1.O[si], c1.D[si], c1.TM[si], c1.S[si], rgb, T,
+                               to_dev(g_rgb, dev), to_dev(g_T, dev), p, dist=dist,
+                               g_dist=to_dev(g_dist, dev))
+    for g, w, name in zip(got, want, ("sites", "density", "texels")):
+        assert_grad_close(g.cpu().numpy(), w, name)
+
+
+def test_autograd_distortion(dev, c1):
+    from paper_2608_17682_amd.autograd import render as vrender
+    sites = c1.ds.sites.clone().requires_grad_(True)
+    rho = torch.log(c1.ds.density.clone()).requires_grad_(True)
+    tex = c1.ds.texels.clone().requires_grad_(True)
+    announce("autograd render with distortion")
+    rgb, T, ld = vrender(sites, torch.exp(rho), tex, c1.ds.nbr_off, c1.ds.nbr_idx, c1.O, c1.D,
+                         c1.TM, c1.S, distortion=True)
+    lam = 0.37
+    (rgb.sum() + lam * ld.sum()).backward()
+    deg = np.array([degenerate(r, 1e-4, float(c1.tm[0])) for r in c1.recs])
+    assert deg.mean() < 0.01
+    R = len(c1.o)
+    gs, gd, gt = adjoint.grad_rays(c1.scene.sites, c1.scene.density, c1.scene.texels, c1.o,
+                                   c1.d, c1.tm, c1.recs, np.ones((R, 3)), np.zeros(R),
+                                   np.full(R, lam))
+    np.testing.assert_allclose(ld.detach().cpu().numpy(), [r.dist for r in c1.recs], atol=2e-6,
+                               rtol=1e-4)
+    assert_grad_close(rho.grad.cpu().numpy(), gd * c1.scene.density, "rho")
+    assert_grad_close(sites.grad.cpu().numpy(), gs, "sites")
+
+
 @pytest.mark.parametrize("schedule", [voro.SCHEDULE_GRID, voro.SCHEDULE_PERSISTENT])
 def test_autograd_views_equals_explicit(dev, c1, schedule):
     # render_views (in-kernel rays, one launch each way) and render over the
