@@ -125,6 +125,15 @@ def bench_config3(scene, dev, args, timed):
                         voro.default_params(img_w=cam.width))
         (rgb * g).sum().backward()
 
+    def step_explicit_dist():
+        # the training objective with the distortion regulariser (Sec. 5.3)
+        reset()
+        O, D, TM = voro.voro_gen_rays(ccam, dev)
+        S = voro.voro_locate_origins(ds, O[:1]).expand(O.shape[0]).contiguous()
+        rgb, T, ld = render(sites, torch.exp(rho), tex, ds.nbr_off, ds.nbr_idx, O, D, TM, S,
+                            voro.default_params(img_w=cam.width), distortion=True)
+        ((rgb * g).sum() + 0.01 * ld.sum()).backward()
+
     # instrumented forward for the step counts
     st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
     voro.voro_prepare(ds)
@@ -133,12 +142,15 @@ def bench_config3(scene, dev, args, timed):
     steps = max(2, args.steps // 2)
     s = timed(step_views, steps, 1)
     se = timed(step_explicit, steps, 1)
+    sd = timed(step_explicit_dist, steps, 1)
     fwd_s = timed(lambda: voro.voro_render_views_fwd(ds, ccam, pf), steps, 1)
     return {"workload": "ellipsoids2M: 1.8M sites on 20 ellipsoid surfaces (sigma 50) + 200k "
                         "uniform [-4,4]^3 (sigma 0.01), 8x8 f32 texels, 1280x840 interior "
                         "pinhole, tmax 14, fwd+bwd via torch.autograd.Function",
             "fwd_bwd_mrays_s": round(cam.n_rays * steps / s / 1e6, 2),
             "fwd_bwd_explicit_rays_mrays_s": round(cam.n_rays * steps / se / 1e6, 2),
+            "fwd_bwd_explicit_rays_with_distortion_mrays_s": round(cam.n_rays * steps / sd / 1e6,
+                                                                   2),
             "fwd_kernel_mrays_s": round(cam.n_rays * steps / fwd_s / 1e6, 2),
             "ms_per_step": round(s * 1e3 / steps, 3),
             "mean_cells_per_ray": round(stats["steps"] / max(1, stats["rays"]), 2)}
@@ -367,6 +379,35 @@ def main():
         s = timed(fb, max(2, args.steps // 2), 1)
         extras["fwd_bwd_f32_mrays_s"] = round(rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
         del gs, gd, gt
+        # cell-skip sweep (Sec. 5.6 / the supplementary threshold table): the
+        # colour of a segment with weight below skip_w is not looked up
+        sweep = []
+        ref_rgb = torch.empty((N_POSES, npx, 3), device=dev)
+        for i in range(N_POSES):
+            frame(i, params, ds, out_rgb=ref_rgb[i])
+        for sw in (0.0, 1e-5, 1e-4, 3e-4, 1e-3, 3e-3, 1e-2):
+            q = voro.voro_params.from_buffer_copy(params)
+            q.skip_w = sw
+            s = timed(lambda: step(ds, q), args.steps, args.warmup)
+            err = 0.0
+            for i in range(N_POSES):
+                frame(i, q, ds)
+                err = max(err, float((rgb - ref_rgb[i]).abs().max()))
+            sweep.append({"skip_w": sw, "mrays_s": round(rays_per_step * args.steps / s / 1e6, 2),
+                          "max_abs_rgb_change": err})
+        extras["skip_sweep"] = sweep
+        del ref_rgb
+        # motion blur (Sec. 6.5): 2 views of 960x540 pixels x 5 time samples
+        # in one launch, pixel = mean of its samples
+        mb = [voro.camera_of(c) for c in synth.motion_blur_cameras(1.0, spp=5)]
+        mb_rays, mb_px = voro.voro_camera_counts(mb)
+        mb_rgb = torch.empty((mb_px, 3), device=dev)
+        mb_T = torch.empty(mb_px, device=dev)
+        mb_ray = torch.empty((mb_rays, 4), device=dev)
+        s = timed(lambda: voro.voro_render_views_fwd(ds, mb, params, mb_rgb, mb_T, mb_ray),
+                  args.steps, args.warmup)
+        extras["motion_blur_2x960x540x5_fwd_mrays_s"] = round(mb_rays * args.steps / s / 1e6, 2)
+        del mb_rgb, mb_T, mb_ray
         # the paper's full appearance model (Sec. 5.1/5.2): surface + view maps
         # of seeded logits, same scene, walk and launches
         full = torch.from_numpy(synth.full_texels(scene.n, scene.tex_res, seed=2)).to(dev)

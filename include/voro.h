@@ -69,7 +69,8 @@ enum {
   VORO_CAM_PINHOLE = 0,         /* f = (W/2)/tan(fov/2), fov horizontal */
   VORO_CAM_FISHEYE = 1,         /* equidistant: theta = r/f, f = (W/2)/(fov/2) */
   VORO_CAM_ROLLING_SHUTTER = 2, /* row y exposed at centre c + y/(H-1) * rs_delta */
-  VORO_CAM_THIN_LENS = 3        /* spp aperture samples per pixel, averaged */
+  VORO_CAM_THIN_LENS = 3,       /* spp aperture samples per pixel, averaged */
+  VORO_CAM_MOTION_BLUR = 4      /* spp time samples over the exposure, averaged */
 };
 
 /* indices into the optional uint64 stats array */
@@ -170,20 +171,23 @@ enum { VORO_SCHEDULE_DEFAULT = 0, VORO_SCHEDULE_GRID = 1, VORO_SCHEDULE_PERSISTE
  * is sampled at its centre (x + 0.5, y + 0.5).  tmax is the ray extent.
  * Thin lens: spp = g*g stratum-centre samples mapped to the lens disk by the
  * concentric map (Shirley and Chiu 1997), each aimed at the pixel's pinhole
- * point on the plane at focus_dist along the axis.  Fisheye pixels outside
+ * point on the plane at focus_dist along the axis.  Motion blur (Sec. 6.5:
+ * time samples over the exposure, averaged): pinhole rays, sample s taken at
+ * tau = (s + 0.5)/spp with the centre moved to c + tau * rs_delta (the
+ * translation over the exposure; orientation fixed).  Fisheye pixels outside
  * the image circle emit no ray (tmax = 0: rgb = 0, T = 1).
  */
 typedef struct voro_camera {
   int32_t model;   /* VORO_CAM_* */
   int32_t width;   /* >= 1 */
   int32_t height;  /* >= 1 (>= 2 for rolling shutter) */
-  int32_t spp;     /* 1, or a square number <= 64 for VORO_CAM_THIN_LENS */
+  int32_t spp;     /* 1; a square <= 64 for THIN_LENS; 1..64 for MOTION_BLUR */
   float c2w[12];
   float fov;       /* radians, in (0, pi) for pinhole-type, (0, 2pi) fisheye */
   float tmax;      /* > 0 */
   float lens_radius;
   float focus_dist;
-  float rs_delta[3];
+  float rs_delta[3]; /* rolling shutter: first -> last row; motion blur: over the exposure */
   int32_t reserved; /* must be 0 */
 } voro_camera;
 

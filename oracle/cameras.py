@@ -55,7 +55,7 @@ def camera_rays(model, width, height, c2w, fov, tmax, rs_delta=(0.0, 0.0, 0.0),
     Rm, c = M[:, :3], M[:, 3]
     px, py = _pixel_grid(W, H)
     n = W * H
-    if model in (0, 2, 3):
+    if model in (0, 2, 3, 4):
         f = (W / 2.0) / math.tan(fov / 2.0)
         dc = np.stack([(px - W / 2.0) / f, (py - H / 2.0) / f, np.ones(n)], 1)
     if model == 0:          # pinhole
@@ -99,6 +99,15 @@ def camera_rays(model, width, height, c2w, fov, tmax, rs_delta=(0.0, 0.0, 0.0),
         # order: pixel-major, then sample
         o = np.stack(os_, 1).reshape(n * spp, 3)
         d = np.stack(ds_, 1).reshape(n * spp, 3)
+        valid = np.ones(n * spp, bool)
+        n = n * spp
+    elif model == 4:        # motion blur
+        d1 = dc @ Rm.T
+        d1 /= np.linalg.norm(d1, axis=1, keepdims=True)
+        delta = np.asarray(rs_delta, np.float64)
+        os_ = [np.broadcast_to(c + ((k + 0.5) / spp) * delta, (n, 3)) for k in range(spp)]
+        o = np.stack(os_, 1).reshape(n * spp, 3)
+        d = np.repeat(d1, spp, axis=0)
         valid = np.ones(n * spp, bool)
         n = n * spp
     else:

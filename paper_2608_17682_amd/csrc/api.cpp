@@ -142,7 +142,7 @@ voro_status check_cameras(const voro_camera* cams, int32_t V, int64_t* n_rays,
   int64_t nr = 0, np = 0;
   for (int v = 0; v < V; ++v) {
     const voro_camera& c = cams[v];
-    if (c.model < VORO_CAM_PINHOLE || c.model > VORO_CAM_THIN_LENS)
+    if (c.model < VORO_CAM_PINHOLE || c.model > VORO_CAM_MOTION_BLUR)
       return fail(VORO_EINVAL, "camera %d: unknown model %d", v, c.model);
     if (c.width < 1 || c.height < 1 || c.width > 65536 || c.height > 65536)
       return fail(VORO_EINVAL, "camera %d: bad size %dx%d", v, c.width, c.height);
@@ -154,6 +154,9 @@ voro_status check_cameras(const voro_camera* cams, int32_t V, int64_t* n_rays,
         return fail(VORO_EINVAL, "camera %d: spp must be a square number in [1, 64]", v);
       if (!(c.lens_radius >= 0.0f) || !(c.focus_dist > 0.0f))
         return fail(VORO_EINVAL, "camera %d: need lens_radius >= 0 and focus_dist > 0", v);
+    } else if (c.model == VORO_CAM_MOTION_BLUR) {
+      if (c.spp < 1 || c.spp > 64)
+        return fail(VORO_EINVAL, "camera %d: spp must be in [1, 64] for motion blur", v);
     } else if (c.spp != 1) {
       return fail(VORO_EINVAL, "camera %d: spp must be 1 for this model", v);
     }

@@ -1,5 +1,6 @@
 // Ray generation per camera model (Sec. 6.5 / App. D: only ray generation
-// changes between pinhole, fisheye, rolling shutter and depth of field).
+// changes between pinhole, fisheye, rolling shutter, depth of field and
+// motion blur).
 // One device function serves voro_gen_rays and the persistent multi-view
 // kernels, so both produce bit-identical rays.
 #pragma once
@@ -16,7 +17,9 @@ struct CamTable {
   int ray_off[VORO_MAX_VIEWS + 1];   // first ray of each view
   int pix_off[VORO_MAX_VIEWS + 1];   // first pixel of each view
   int tile_off[VORO_MAX_VIEWS + 1];  // first work tile of each view (persistent launch)
-  int g[VORO_MAX_VIEWS];             // samples per pixel side (spp = g*g)
+  int g[VORO_MAX_VIEWS];             // thin lens: samples per pixel side (spp = g*g)
+  int gx[VORO_MAX_VIEWS];            // a pixel's samples laid out as a gx x gy block
+  int gy[VORO_MAX_VIEWS];            // of the view's sample grid (spp = gx*gy)
   int V;
 };
 
@@ -97,8 +100,11 @@ __device__ __forceinline__ bool gen_ray(const voro_camera& c, int g, int px, int
       cy = y;
       cz = 1.0f;
     }
-    if (c.model == VORO_CAM_ROLLING_SHUTTER) {
-      const float sr = (float)py / (H - 1.0f);
+    if (c.model == VORO_CAM_ROLLING_SHUTTER || c.model == VORO_CAM_MOTION_BLUR) {
+      // rolling shutter: the row's exposure time; motion blur: the sample's
+      const float sr = c.model == VORO_CAM_ROLLING_SHUTTER
+                           ? (float)py / (H - 1.0f)
+                           : ((float)s + 0.5f) / (float)c.spp;
       ox = fmaf(sr, c.rs_delta[0], ox);
       oy = fmaf(sr, c.rs_delta[1], oy);
       oz = fmaf(sr, c.rs_delta[2], oz);

@@ -123,18 +123,19 @@ __device__ __forceinline__ bool tile_ray(const CamTable& ct, int unit, int sx, i
   // the unit is wave-uniform: keep the camera in scalar registers
   const int v = __builtin_amdgcn_readfirstlane(find_view(ct.tile_off, ct.V, unit));
   const voro_camera& c = ct.cam[v];
-  const int g = ct.g[v];
-  const int gw = c.width * g;
-  const int gh = c.height * g;
+  const int gx = ct.gx[v];
+  const int gy = ct.gy[v];
+  const int gw = c.width * gx;
+  const int gh = c.height * gy;
   const int units_x = (gw + unit_w - 1) / unit_w;
   const int local = unit - ct.tile_off[v];
   const int X = (local % units_x) * unit_w + sx * tile_w + grp % tile_w;
   const int Y = (local / units_x) * unit_h + sy * tile_h + grp / tile_w;
   if (X >= gw || Y >= gh) return false;
   tr.view = v;
-  tr.px = X / g;
-  tr.py = Y / g;
-  tr.s = (X % g) + g * (Y % g);
+  tr.px = X / gx;
+  tr.py = Y / gy;
+  tr.s = (X % gx) + gx * (Y % gy);
   tr.pixel = tr.py * c.width + tr.px;
   tr.ray = ct.ray_off[v] + tr.pixel * c.spp + tr.s;
   return true;
@@ -145,7 +146,7 @@ __device__ __forceinline__ RayIn views_ray(const ViewsArgs& a, const TileRay& tr
   RayIn r;
   gen_ray(c, a.ct.g[tr.view], tr.px, tr.py, tr.s, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, r.tmax);
   r.start = a.center_cell[tr.view];
-  const bool moved = c.model == VORO_CAM_ROLLING_SHUTTER ||
+  const bool moved = c.model == VORO_CAM_ROLLING_SHUTTER || c.model == VORO_CAM_MOTION_BLUR ||
                      (c.model == VORO_CAM_THIN_LENS && c.lens_radius > 0.0f);
   if (moved && r.tmax > 0.0f && r.start >= 0 && r.start < a.s.n)
     r.start = nearest_walk(a.s, r.ox, r.oy, r.oz, r.start, capped);
@@ -313,13 +314,16 @@ static CamTable make_table(const voro_camera* cams, int V, int tile_w, int tile_
     ct.cam[v] = cams[v];
     const int g = (int)std::lround(std::sqrt((double)cams[v].spp));
     ct.g[v] = g;
+    // thin-lens samples tile the pixel as g x g; time samples as a row
+    ct.gx[v] = cams[v].model == VORO_CAM_THIN_LENS ? g : cams[v].spp;
+    ct.gy[v] = cams[v].model == VORO_CAM_THIN_LENS ? g : 1;
     ct.ray_off[v] = ro;
     ct.pix_off[v] = po;
     ct.tile_off[v] = to;
     ro += cams[v].width * cams[v].height * cams[v].spp;
     po += cams[v].width * cams[v].height;
     if (tile_w > 0) {
-      const int gw = cams[v].width * g, gh = cams[v].height * g;
+      const int gw = cams[v].width * ct.gx[v], gh = cams[v].height * ct.gy[v];
       to += ((gw + tile_w - 1) / tile_w) * ((gh + tile_h - 1) / tile_h);
     }
   }

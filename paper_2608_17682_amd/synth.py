@@ -28,6 +28,7 @@ PINHOLE = 0
 FISHEYE = 1          # equidistant fisheye, theta = r / f
 ROLLING_SHUTTER = 2  # per-row camera centre c0 + s * delta, s = row / (H - 1)
 THIN_LENS = 3        # depth of field, spp aperture samples per pixel
+MOTION_BLUR = 4      # spp time samples over the exposure
 
 
 @dataclasses.dataclass
@@ -57,10 +58,10 @@ class Camera:
     c2w: np.ndarray            # [3,4] float64: columns = right, down, forward, centre
     fov: float                 # radians; pinhole: horizontal FOV, fisheye: full FOV
     tmax: float
-    rs_delta: tuple = (0.0, 0.0, 0.0)   # rolling shutter: world-space centre shift over the frame
+    rs_delta: tuple = (0.0, 0.0, 0.0)   # rolling shutter / motion blur: centre shift over the frame / exposure
     lens_radius: float = 0.0           # thin lens
     focus_dist: float = 1.0            # thin lens, along the optical axis
-    spp: int = 1                       # thin lens samples per pixel (a square number)
+    spp: int = 1                       # samples per pixel (thin lens: a square; motion blur: times)
 
     @property
     def n_pixels(self) -> int:
@@ -260,6 +261,20 @@ def config5_cameras(scale=1.0) -> List[Camera]:
             w, h = sz(640, 480)
             cams.append(Camera(THIN_LENS, w, h, pose, math.radians(60.0), 8.0,
                                lens_radius=0.05, focus_dist=3.0, spp=4))
+    return cams
+
+
+def motion_blur_cameras(scale=1.0, spp=5) -> List[Camera]:
+    """Two motion-blurred pinhole views on the radius-3 orbit (960x540 at scale
+    1), spp time samples over an exposure that moves the centre by 0.15 along
+    the camera's +x and 0.05 along its +z."""
+    cams = []
+    for k in (1, 5):
+        pose = orbit_pose(2.0 * math.pi * k / 8 + 0.2)
+        w, h = max(2, int(round(960 * scale))), max(2, int(round(540 * scale)))
+        delta = tuple(float(x) for x in 0.15 * pose[:, 0] + 0.05 * pose[:, 2])
+        cams.append(Camera(MOTION_BLUR, w, h, pose, math.radians(60.0), 8.0, rs_delta=delta,
+                           spp=spp))
     return cams
 
 

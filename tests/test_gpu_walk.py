@@ -179,8 +179,8 @@ def test_skip_matches_oracle(dev, c1):
 
 
 def test_gen_rays_match_oracle(dev):
-    cams = synth.config5_cameras(scale=0.1)
-    announce("gen_rays 8 mixed cameras")
+    cams = synth.config5_cameras(scale=0.1) + synth.motion_blur_cameras(scale=0.08)
+    announce("gen_rays 8 mixed cameras + 2 motion blur")
     O, D, TM = voro.voro_gen_rays(cams, dev)
     O, D, TM = O.cpu().numpy(), D.cpu().numpy(), TM.cpu().numpy()
     off = 0
@@ -258,7 +258,7 @@ def test_autograd_function(dev, c1):
 def test_views_fwd_equals_explicit_rays(dev, c1):
     # the persistent multi-view launch generates the same rays, starts in the
     # same cells and takes the same walk as gen_rays + locate + render_fwd
-    cams = synth.config5_cameras(scale=0.06)
+    cams = synth.config5_cameras(scale=0.06) + synth.motion_blur_cameras(scale=0.05)
     for cm in cams:
         cm.tmax = 4.0
     announce("views fwd vs explicit, 8 mixed cameras")
@@ -289,7 +289,7 @@ def test_views_fwd_equals_explicit_rays(dev, c1):
 
 
 def test_views_match_oracle_sampled(dev, c1):
-    cams = synth.config5_cameras(scale=0.06)
+    cams = synth.config5_cameras(scale=0.06) + synth.motion_blur_cameras(scale=0.05)
     for cm in cams:
         cm.tmax = 4.0
     announce("views fwd vs oracle, sampled pixels")
@@ -312,7 +312,7 @@ def test_views_match_oracle_sampled(dev, c1):
 
 
 def test_views_bwd_equals_explicit(dev, c1):
-    cams = [cm for cm in synth.config5_cameras(scale=0.05)]
+    cams = synth.config5_cameras(scale=0.05) + synth.motion_blur_cameras(scale=0.04, spp=3)
     for cm in cams:
         cm.tmax = 4.0
     nr = [cm.n_rays for cm in cams]

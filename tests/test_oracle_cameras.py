@@ -117,3 +117,25 @@ def test_concentric_disk_map():
     assert cameras.concentric_disk(0.5, 0.5) == (0.0, 0.0)
     x, y = cameras.concentric_disk(1.0, 0.5)
     assert x == pytest.approx(1.0) and y == pytest.approx(0.0, abs=1e-15)
+
+
+def test_motion_blur_samples_are_pinholes_at_moved_centres():
+    # sample s of a pixel is the pinhole ray of the camera moved to
+    # c + (s + 0.5)/spp * delta; delta = 0 repeats the pinhole ray spp times
+    W, H, fov, spp = 9, 7, math.radians(60), 5
+    M = pose()
+    delta = np.array([0.2, -0.1, 0.05])
+    o, d, tm, valid = cameras.camera_rays(4, W, H, M, fov, 6.0, rs_delta=delta, spp=spp)
+    assert len(o) == W * H * spp and valid.all()
+    for s in range(spp):
+        Ms = M.copy()
+        Ms[:, 3] = M[:, 3] + (s + 0.5) / spp * delta
+        op, dp, _, _ = cameras.camera_rays(0, W, H, Ms, fov, 6.0)
+        np.testing.assert_allclose(o[s::spp], op, atol=1e-15)
+        np.testing.assert_allclose(d[s::spp], dp, atol=1e-15)
+    o0, d0, _, _ = cameras.camera_rays(4, W, H, M, fov, 6.0, spp=3)
+    op, dp, _, _ = cameras.camera_rays(0, W, H, M, fov, 6.0)
+    np.testing.assert_array_equal(o0, np.repeat(op, 3, 0))
+    np.testing.assert_array_equal(d0, np.repeat(dp, 3, 0))
+    # the middle sample of an odd count sits at mid-exposure
+    np.testing.assert_allclose(o[2], M[:, 3] + 0.5 * delta, atol=1e-15)
