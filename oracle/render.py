@@ -13,6 +13,8 @@ Sec. 5.2), c_k = sigmoid(T_vi(oct(d_k)) + T_vd(oct(-w))) with texels laid
 out [N, 2, R, R, 4] (map 0 = T_vi, map 1 = T_vd), d_k the unit direction from
 the site to the hit point x_k and -w the direction from x_k back towards
 the ray's origin.  Readings of what the paper leaves open:
+* appearance 2 is the spherical-harmonic colour of Sec. 3.3 at the ray
+  direction (``sh``; coefficients [N, 48]), the comparison model;
 * the hit point is where the ray enters the cell, x_k = o + t_k w; in the
   start cell, which holds the origin, it is where the ray leaves it,
   o + min(exit_0, tmax) w; a hit point on the site itself (d undefined)
@@ -36,7 +38,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import appearance as appearance_mod, distortion, walk
+from . import appearance as appearance_mod, distortion, sh, walk
 
 
 @dataclasses.dataclass
@@ -70,13 +72,15 @@ def render_ray(sites, density, texels, o, w, tmax, t_stop=1e-4, skip_w=0.0,
                max_steps=4096, start=None, method="stepwise", appearance=0) -> RayRecord:
     """Render one ray by brute force.  method: 'stepwise' or 'interval'."""
     appearance_model = int(appearance)
-    if appearance_model not in (0, 1):
+    if appearance_model not in (0, 1, 2):
         raise ValueError(f"appearance {appearance}")
     sites = walk.as64(sites)
     sig = walk.as64(density)
     tex = np.asarray(texels)
     if appearance_model == 1 and (tex.ndim != 5 or tex.shape[1] != 2):
         raise ValueError("appearance 1 needs texels [N, 2, R, R, 4]")
+    if appearance_model == 2 and (tex.ndim != 2 or tex.shape[1] != 48):
+        raise ValueError("appearance 2 needs SH coefficients [N, 48]")
     o = walk.as64(o)
     w = walk.as64(w)
     tmax = float(tmax)
@@ -122,6 +126,8 @@ def render_ray(sites, density, texels, o, w, tmax, t_stop=1e-4, skip_w=0.0,
         else:
             if appearance_model == 1:
                 c = appearance_mod.full_colour(tex[i, 0], tex[i, 1], d_surf, -w)
+            elif appearance_model == 2:
+                c = sh.sh_colour(tex[i], w)
             else:
                 c = appearance_mod.lookup(tex[i], w)
             C = C + wk * c

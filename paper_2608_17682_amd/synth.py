@@ -345,6 +345,18 @@ def full_texels(n: int, res: int, seed: int, vi_scale: float = 1.5,
     return tex
 
 
+def sh_coeffs(n: int, seed: int) -> np.ndarray:
+    """Seeded degree-3 spherical-harmonic colour coefficients [n, 48] f32
+    (coefficient-major RGB): a base colour U[0.2, 0.8] in the l = 0 term and
+    N(0, (0.15 / 2^l)^2) higher orders."""
+    rng = np.random.default_rng(7000 + seed)
+    k = np.zeros((n, 16, 3), np.float32)
+    k[:, 0, :] = rng.uniform(0.2, 0.8, (n, 3)) * (2.0 * math.sqrt(math.pi))
+    for l in range(1, 4):
+        k[:, l * l:(l + 1) * (l + 1), :] = rng.normal(0.0, 0.15 / 2 ** l, (n, 2 * l + 1, 3))
+    return k.reshape(n, 48)
+
+
 def texels_rgb(n: int, res: int, rgb) -> np.ndarray:
     tex = np.zeros((n, res, res, 4), np.float32)
     tex[..., :3] = np.asarray(rgb, np.float32)
