@@ -104,12 +104,16 @@ enum {
  *           [N,2,R,R,4]   with tex_maps = 2: map 0 = surface map T_vi, map 1 =
  *                         view map T_vd, both RGB logits (Sec. 5.1, 5.2;
  *                         appearance 1)
+ *           [N,48]        with tex_maps = 3: degree-3 spherical-harmonic RGB
+ *                         coefficients, coefficient-major, index l^2 + l + m
+ *                         (Sec. 3.3; appearance 2, forward only; 16-byte
+ *                         aligned; tex_res is not used but must be valid)
  */
 typedef struct voro_scene {
   int32_t n_sites;   /* N >= 1 */
   int32_t tex_res;   /* R in [VORO_MIN_TEX_RES, VORO_MAX_TEX_RES] */
   int32_t tex_dtype; /* VORO_TEX_* */
-  int32_t tex_maps;  /* texture maps per cell: 0 or 1 = one, 2 = surface + view */
+  int32_t tex_maps;  /* per-cell appearance: 0/1 = one map, 2 = surface + view, 3 = SH */
   int64_t n_edges;   /* M = nbr_off[N]; M + 3 N < 2^31 */
   const float* sites;
   const float* density;
@@ -133,6 +137,9 @@ typedef struct voro_scene {
  *               where the ray meets the cell - its entry point, or in the
  *               start cell (which holds the origin) its exit point clipped
  *               at tmax; x = p_i uses the ray direction instead of x - p_i
+ *               2 = degree-3 spherical harmonics at the ray direction, the
+ *               comparison model of Sec. 3.3 (needs tex_maps = 3; forward
+ *               only)
  *   lanes_per_ray  1, 2, 4, 8 or 16 lanes cooperate on one ray's
  *               neighbour tests (0 = library default)                   [0]
  *   tile_w, tile_h  screen tile walked by one 64-lane wave, in rays;

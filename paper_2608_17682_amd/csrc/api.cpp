@@ -41,8 +41,8 @@ voro_status check_scene(const voro_scene* s) {
   if (s->tex_dtype != VORO_TEX_F32 && s->tex_dtype != VORO_TEX_F16 &&
       s->tex_dtype != VORO_TEX_BF16)
     return fail(VORO_EINVAL, "unknown tex_dtype %d", s->tex_dtype);
-  if (s->tex_maps < 0 || s->tex_maps > 2)
-    return fail(VORO_EINVAL, "tex_maps must be 0, 1 or 2 (got %d)", s->tex_maps);
+  if (s->tex_maps < 0 || s->tex_maps > 3)
+    return fail(VORO_EINVAL, "tex_maps must be 0, 1, 2 or 3 (got %d)", s->tex_maps);
   if (s->n_edges < 0 || s->n_edges + 3 * (int64_t)s->n_sites >= ((int64_t)1 << 31))
     return fail(VORO_EINVAL, "n_edges %lld out of range (n_edges + 3 n_sites must be < 2^31)",
                 (long long)s->n_edges);
@@ -78,9 +78,11 @@ voro_status check_params(const voro_params* p, bool backward) {
   if (p->max_steps < 1) return fail(VORO_EINVAL, "max_steps must be >= 1");
   if (!(p->tie_window >= 0.0f) || !std::isfinite(p->tie_window))
     return fail(VORO_EINVAL, "tie_window must be finite and >= 0");
-  if (p->appearance != 0 && p->appearance != 1)
+  if (p->appearance < 0 || p->appearance > 2)
     return fail(VORO_EUNSUPPORTED, "appearance %d not built (0 = ray-direction texture, "
-                "1 = surface + view maps)", p->appearance);
+                "1 = surface + view maps, 2 = degree-3 spherical harmonics)", p->appearance);
+  if (backward && p->appearance == 2)
+    return fail(VORO_EUNSUPPORTED, "the spherical-harmonic comparison model is forward only");
   const int l = p->lanes_per_ray;
   if (!(l == 0 || l == 1 || l == 2 || l == 4 || l == 8 || l == 16))
     return fail(VORO_EINVAL, "lanes_per_ray must be 0, 1, 2, 4, 8 or 16");
@@ -106,6 +108,14 @@ voro_status check_params(const voro_params* p, bool backward) {
 // The texel layout must match the appearance model, and gradient record
 // keys (cell * maps + map) * R^2 + quad must fit an int.
 voro_status check_appearance(const voro_scene* s, const voro_params* p) {
+  if (s->tex_maps == 3 || p->appearance == 2) {
+    if (s->tex_maps != 3 || p->appearance != 2)
+      return fail(VORO_EINVAL, "spherical-harmonic coefficients (tex_maps = 3) go with "
+                  "appearance 2 and only with it");
+    if (!aligned(s->texels, 16))
+      return fail(VORO_EINVAL, "spherical-harmonic coefficients must be 16-byte aligned");
+    return VORO_OK;
+  }
   const int maps = s->tex_maps == 2 ? 2 : 1;
   if (p->appearance == 1 && maps != 2)
     return fail(VORO_EINVAL, "appearance 1 needs two texture maps per cell (tex_maps = 2)");

@@ -343,10 +343,14 @@ static int persistent_blocks(bool backward, int block) {
   int dev = 0, cus = 0, occ = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (backward)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX, APP, true>, block, 0);
-  else
+  if constexpr (APP == 2) {
+    (void)backward;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block, 0);
+  } else if (backward) {
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX, APP, true>, block, 0);
+  } else {
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block, 0);
+  }
   (void)hipGetLastError();
   c = max(kXcd, max(1, cus) * max(1, occ));
   c = (c / kXcd) * kXcd;
@@ -357,7 +361,16 @@ template <int LPR, int TEX, int APP>
 static void launch_views_t(bool backward, bool persist, const ViewsArgs& a, int block,
                            hipStream_t st) {
   const int nwaves = block / 64;
-  if (persist) {
+  if constexpr (APP == 2) {
+    // forward only: the comparison model has no adjoint (refused on the host)
+    if (persist) {
+      const int blocks = persistent_blocks<LPR, TEX, APP>(false, block);
+      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
+    } else {
+      const int blocks = max(1, (a.total_tiles + nwaves - 1) / nwaves);
+      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block), 0, st, a);
+    }
+  } else if (persist) {
     const int blocks = persistent_blocks<LPR, TEX, APP>(backward, block);
     if (backward)
       hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
@@ -440,6 +453,8 @@ static voro_status views_common(bool backward, const voro_scene* scene, void* ws
   const bool persist = params->schedule == VORO_SCHEDULE_PERSISTENT;
   if (params->appearance == 1)
     launch_views_tex<1>(scene->tex_dtype, L.lpr, backward, persist, a, block, s);
+  else if (params->appearance == 2)
+    launch_views_tex<2>(scene->tex_dtype, L.lpr, backward, persist, a, block, s);
   else
     launch_views_tex<0>(scene->tex_dtype, L.lpr, backward, persist, a, block, s);
   return check_launch(backward ? "voro_render_views_bwd" : "voro_render_views_fwd");

@@ -203,7 +203,7 @@ voro_status voro_morton_reorder(const voro_scene* in, const voro_scene* out, int
   if ((st = check_scene(out)) != VORO_OK) return st;
   if (out->n_sites != in->n_sites || out->n_edges != in->n_edges ||
       out->tex_res != in->tex_res || out->tex_dtype != in->tex_dtype ||
-      (out->tex_maps == 2) != (in->tex_maps == 2))
+      (out->tex_maps == 2) != (in->tex_maps == 2) || (out->tex_maps == 3) != (in->tex_maps == 3))
     return fail(VORO_EINVAL, "out scene must match in scene sizes and texel type");
   if (!perm || !inv_perm) return fail(VORO_EINVAL, "perm and inv_perm must not be NULL");
   const int n = in->n_sites;
@@ -239,8 +239,10 @@ voro_status voro_morton_reorder(const voro_scene* in, const voro_scene* out, int
   hipLaunchKernelGGL(k_permute_rows, dim3((int)(((long)n * 16 + 255) / 256)), dim3(256), 0, s, perm,
                      inv_perm, n, (int)in->n_edges, in->nbr_off, in->nbr_idx, off_out, const_cast<int*>(out->nbr_idx));
   const int esz = in->tex_dtype == VORO_TEX_F32 ? 4 : 2;
+  // texel maps [R,R,4] per map, or 48 spherical-harmonic coefficients
   const int maps = in->tex_maps == 2 ? 2 : 1;
-  const long bytes_per_cell = (long)maps * in->tex_res * in->tex_res * 4 * esz;  // multiple of 16
+  const long bytes_per_cell = in->tex_maps == 3 ? 48L * esz
+                                                : (long)maps * in->tex_res * in->tex_res * 4 * esz;
   const int words = (int)(bytes_per_cell / 16);
   const long n_words = (long)n * words;
   hipLaunchKernelGGL(k_permute_texels, dim3((int)((n_words + 255) / 256)), dim3(256), 0, s, perm,

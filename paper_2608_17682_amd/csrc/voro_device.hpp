@@ -362,6 +362,79 @@ __device__ __forceinline__ void oct_jacobian(float dx, float dy, float dz, float
   }
 }
 
+// --------------------------------------- spherical-harmonic comparison
+//
+// Sec. 3.3: c = sum_{l<=3} sum_m k_lm Y_l^m(w) with the real orthonormal
+// harmonics (no Condon-Shortley phase), coefficient i = l^2 + l + m, stored
+// per cell as 48 values (coefficient-major RGB).  The constants are the
+// normalisations of the polynomial forms: 1/(2 sqrt(pi)); sqrt(3/(4 pi));
+// sqrt(15/pi)/2, sqrt(5/pi)/4, sqrt(15/pi)/4; sqrt(35/(2 pi))/4,
+// sqrt(105/pi)/2, sqrt(21/(2 pi))/4, sqrt(7/pi)/4, sqrt(105/pi)/4.
+__device__ __forceinline__ void sh3_basis(float x, float y, float z, float Y[16]) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = 0.28209479177387814f;
+  Y[1] = 0.48860251190291992f * y;
+  Y[2] = 0.48860251190291992f * z;
+  Y[3] = 0.48860251190291992f * x;
+  Y[4] = 1.0925484305920792f * (x * y);
+  Y[5] = 1.0925484305920792f * (y * z);
+  Y[6] = 0.31539156525252005f * fmaf(3.0f, zz, -1.0f);
+  Y[7] = 1.0925484305920792f * (x * z);
+  Y[8] = 0.54627421529603959f * (xx - yy);
+  Y[9] = 0.59004358992664352f * (y * fmaf(3.0f, xx, -yy));
+  Y[10] = 2.8906114426405538f * (x * y * z);
+  Y[11] = 0.45704579946446572f * (y * fmaf(5.0f, zz, -1.0f));
+  Y[12] = 0.37317633259011540f * (z * fmaf(5.0f, zz, -3.0f));
+  Y[13] = 0.45704579946446572f * (x * fmaf(5.0f, zz, -1.0f));
+  Y[14] = 1.4453057213202769f * (z * (xx - yy));
+  Y[15] = 0.59004358992664352f * (x * fmaf(-3.0f, yy, xx));
+}
+
+// the 48 coefficients of cell i, streamed in 16-byte loads (12 for f32, 6
+// for f16/bf16), dotted with the basis
+template <int TEX>
+__device__ __forceinline__ void sh3_colour(const void* __restrict__ tex, int i, const float Y[16],
+                                           float& r, float& g, float& b) {
+  float v[48];
+  if constexpr (TEX == VORO_TEX_F32) {
+    const float4* p = reinterpret_cast<const float4*>(tex) + (size_t)i * 12;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      const float4 a = p[q];
+      v[4 * q] = a.x;
+      v[4 * q + 1] = a.y;
+      v[4 * q + 2] = a.z;
+      v[4 * q + 3] = a.w;
+    }
+  } else {
+    const uint4* p = reinterpret_cast<const uint4*>(tex) + (size_t)i * 6;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const uint4 a = p[q];
+      const uint2 lo = make_uint2(a.x, a.y), hi = make_uint2(a.z, a.w);
+      const float4 fl = TexelT<TEX>::load(&lo, 0);
+      const float4 fh = TexelT<TEX>::load(&hi, 0);
+      v[8 * q] = fl.x;
+      v[8 * q + 1] = fl.y;
+      v[8 * q + 2] = fl.z;
+      v[8 * q + 3] = fl.w;
+      v[8 * q + 4] = fh.x;
+      v[8 * q + 5] = fh.y;
+      v[8 * q + 6] = fh.z;
+      v[8 * q + 7] = fh.w;
+    }
+  }
+  r = Y[0] * v[0];
+  g = Y[0] * v[1];
+  b = Y[0] * v[2];
+#pragma unroll
+  for (int k = 1; k < 16; ++k) {
+    r = fmaf(Y[k], v[3 * k], r);
+    g = fmaf(Y[k], v[3 * k + 1], g);
+    b = fmaf(Y[k], v[3 * k + 2], b);
+  }
+}
+
 // ---------------------------------------------------------- segment math
 //
 // Sec. 3.2: delta = max(min(exit, tmax) - t_in, 0), alpha = 1 - exp(-sigma

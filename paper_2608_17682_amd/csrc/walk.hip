@@ -205,10 +205,14 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
 template <int LPR, int TEX, int APP>
 static void launch_ray_kernel(bool backward, const RayArgs& a, int blocks, int block,
                               hipStream_t st) {
-  if (backward)
-    hipLaunchKernelGGL((k_render_bwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
-  else
+  if constexpr (APP == 2) {
+    // the spherical-harmonic comparison model has no adjoint (refused on the host)
     hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
+  } else if (backward) {
+    hipLaunchKernelGGL((k_render_bwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
+  }
 }
 
 template <int TEX, int APP>
@@ -237,6 +241,8 @@ static void dispatch_ray_kernel(int app, int tex, int lpr, bool backward, const 
                                 int blocks, int block, hipStream_t st) {
   if (app == 1)
     dispatch_tex<1>(tex, lpr, backward, a, blocks, block, st);
+  else if (app == 2)
+    dispatch_tex<2>(tex, lpr, backward, a, blocks, block, st);
   else
     dispatch_tex<0>(tex, lpr, backward, a, blocks, block, st);
 }

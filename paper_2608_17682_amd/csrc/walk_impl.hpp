@@ -97,7 +97,7 @@ __device__ __forceinline__ void hit_vector(const RayIn& r, const Cell& c, int k,
 }
 
 // The taps a ray uses for every cell: the single map at +w (appearance 0)
-// or the view map at -w (appearance 1).
+// or the view map at -w (appearance 1; unused by appearance 2).
 template <int APP>
 __device__ __forceinline__ Taps ray_taps(const RayIn& r, int R) {
   return APP ? make_taps(-r.dx, -r.dy, -r.dz, R) : make_taps(r.dx, r.dy, r.dz, R);
@@ -120,6 +120,8 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
   }
   cnt.rays++;
   const Taps tp = ray_taps<APP>(r, s.res);
+  float Ysh[16];
+  if constexpr (APP == 2) sh3_basis(r.dx, r.dy, r.dz, Ysh);
   float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, t_in = 0.0f;
   float dP = 0.0f, dQ = 0.0f, dW = 0.0f, dA = 0.0f, s0 = 0.0f;
   int cur = r.start;
@@ -144,6 +146,8 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
       float cr, cg, cb;
       if constexpr (APP == 0) {
         texel_rgb<TEX>(s.texels, cur, s.res, tp, cr, cg, cb);
+      } else if constexpr (APP == 2) {
+        sh3_colour<TEX>(s.texels, cur, Ysh, cr, cg, cb);
       } else {
         float hx, hy, hz;
         hit_vector(r, c, k, t_in, ex.t, hx, hy, hz);

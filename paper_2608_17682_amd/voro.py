@@ -236,6 +236,8 @@ class DeviceScene:
 
     @property
     def tex_res(self):
+        if self.texels.dim() == 2:
+            return 2   # spherical-harmonic coefficients: no texture resolution
         return int(self.texels.shape[-2])
 
     @property
@@ -244,6 +246,10 @@ class DeviceScene:
             if int(self.texels.shape[1]) != 2:
                 raise ValueError("texels [N,2,R,R,4] expected for two maps")
             return 2
+        if self.texels.dim() == 2:
+            if int(self.texels.shape[1]) != 48:
+                raise ValueError("spherical-harmonic coefficients [N,48] expected")
+            return 3
         return 1
 
     def c(self) -> voro_scene:

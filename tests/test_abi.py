@@ -84,7 +84,7 @@ def test_workspace_size_host_only(L):
 
 
 @pytest.mark.parametrize("field,value", [("n_sites", 0), ("tex_res", 1), ("tex_res", 17),
-                                         ("tex_dtype", 7), ("n_edges", -1), ("tex_maps", 3)])
+                                         ("tex_dtype", 7), ("n_edges", -1), ("tex_maps", 4)])
 def test_bad_scene_is_einval(L, field, value):
     s = fake_scene()
     setattr(s, field, value)
@@ -117,14 +117,23 @@ def test_render_validation_before_device(L):
     assert st == voro.VORO_EINVAL
     # bad params
     for field, value in [("max_steps", 0), ("lanes_per_ray", 3), ("block", 100),
-                         ("t_stop", float("nan")), ("appearance", 1), ("appearance", 2)]:
+                         ("t_stop", float("nan")), ("appearance", 1), ("appearance", 2),
+                         ("appearance", 3)]:
         q = voro.default_params(**{field: value})
         st = L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
                                None, None, None, None, None)
         assert st in (voro.VORO_EINVAL, voro.VORO_EUNSUPPORTED), field
-    q = voro.default_params(appearance=2)
+    q = voro.default_params(appearance=3)
     assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
                              None, None, None, None, None) == voro.VORO_EUNSUPPORTED
+    # the spherical-harmonic comparison model is forward only and needs its
+    # coefficient layout
+    q = voro.default_params(appearance=2)
+    assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
+                             None, None, None, None, None) == voro.VORO_EINVAL
+    assert "spherical-harmonic" in voro.last_error()
+    assert L.voro_render_bwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A, A,
+                             None, None, None, A, A, A, None, None) == voro.VORO_EUNSUPPORTED
     # the full appearance model needs two maps per cell, and the single-map
     # model one
     q = voro.default_params(appearance=1)
