@@ -443,6 +443,30 @@ def main():
         fa["fwd_bwd_f32_mrays_s"] = round(rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
         extras["full_appearance"] = fa
         del gs, gd, gt, dsf, full
+        # appearance comparison (Sec. 3.3 vs 5.1/5.2): appearance values and
+        # bytes loaded per visited cell, and forward throughput, same walk
+        ksh = torch.from_numpy(synth.sh_coeffs(scene.n, seed=2)).to(dev)
+        if not args.no_morton:
+            ksh = ksh[perm.long()].contiguous()
+        psh = with_app(params)
+        psh.appearance = 2
+        cmp_ = {"single_map": {"values_per_cell": 12, "bytes_f32": 64, "bytes_f16": 32,
+                               "fwd_f32_mrays_s": round(value, 2),
+                               "fwd_float16_mrays_s": extras.get("fwd_float16_mrays_s")},
+                "surface_plus_view_maps": {"values_per_cell": 24, "bytes_f32": 128,
+                                           "bytes_f16": 64,
+                                           "fwd_f32_mrays_s": fa["fwd_f32_mrays_s"],
+                                           "fwd_float16_mrays_s": fa["fwd_float16_mrays_s"]},
+                "sh_degree3": {"values_per_cell": 48, "bytes_f32": 192, "bytes_f16": 96}}
+        for name, kk in (("f32", ksh), ("float16", voro.voro_cast_texels(ksh, "float16"))):
+            dss = ds.with_arrays(texels=kk)
+            voro.voro_prepare(dss)
+            s = timed(lambda: step(dss, psh), args.steps, args.warmup)
+            cmp_["sh_degree3"][f"fwd_{name}_mrays_s"] = round(rays_per_step * args.steps / s / 1e6,
+                                                              2)
+        extras["appearance_comparison"] = cmp_
+        voro.voro_prepare(ds)
+        del ksh
         log(f"extras: {extras}")
         for name, fn in (("config3", bench_config3), ("config5", bench_config5)):
             if name not in large:
