@@ -327,6 +327,50 @@ __device__ __forceinline__ void table_flush(const GradTable& t, const Grads& g, 
   for (int i = threadIdx.x; i < kTableCap; i += blockDim.x) t.keys[i] = -1;
 }
 
+// Value of lane ^ M, exchanged without the LDS crossbar where gfx950 allows:
+// DPP quad permutations (xor 1, 2), a swizzle (xor 4), DPP row rotation by
+// 8 (xor 8 within a row of 16) and the row/half swaps of permlane16/32
+// (xor 16, 32; element 0 holds the even row / lower half, element 1 the
+// other).  Every lane of the wave must take part.
+template <int M>
+__device__ __forceinline__ int xor_lane(int x, int lane) {
+  if constexpr (M == 1) {
+    return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (M == 2) {
+    return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (M == 4) {
+    return __builtin_amdgcn_ds_swizzle(x, (4 << 10) | 0x1F);          // bit mode, xor 4
+  } else if constexpr (M == 8) {
+    return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false); // row_ror:8
+  } else if constexpr (M == 16) {
+    const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (lane & 16) ? (int)p[0] : (int)p[1];
+  } else {
+    const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (lane & 32) ? (int)p[0] : (int)p[1];
+  }
+}
+
+// One butterfly level: partners holding the same key add up and the upper
+// one retires.  Every lane of the wave must call this.
+template <int M>
+__device__ __forceinline__ void merge_level(int& key, float (&v)[16], int lane) {
+  const int pk = xor_lane<M>(key, lane);
+  const bool match = key >= 0 && pk == key;
+  if (!__any(match)) return;
+  float pv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) pv[i] = __int_as_float(xor_lane<M>(__float_as_int(v[i]), lane));
+  if (match) {
+    if ((lane & M) == 0) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] += pv[i];
+    } else {
+      key = -1;
+    }
+  }
+}
+
 // Merge equal-key records of butterfly partners across the wave (lane ^ m
 // for m = LPR .. 32), then add the survivors to the workgroup table (or, with
 // no table, to global memory).  Every lane of the wave must call this (key <
@@ -349,23 +393,12 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
     v[5 + 3 * t] = q[t] * mg;
     v[6 + 3 * t] = q[t] * mb;
   }
-#pragma unroll
-  for (int m = LPR; m < 64; m <<= 1) {
-    const int pk = __shfl_xor(key, m);
-    const bool match = key >= 0 && pk == key;
-    if (!__any(match)) continue;
-    float pv[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) pv[i] = __shfl_xor(v[i], m);
-    if (match) {
-      if ((lane & m) == 0) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] += pv[i];
-      } else {
-        key = -1;
-      }
-    }
-  }
+  if constexpr (LPR <= 1) merge_level<1>(key, v, lane);
+  if constexpr (LPR <= 2) merge_level<2>(key, v, lane);
+  if constexpr (LPR <= 4) merge_level<4>(key, v, lane);
+  if constexpr (LPR <= 8) merge_level<8>(key, v, lane);
+  if constexpr (LPR <= 16) merge_level<16>(key, v, lane);
+  merge_level<32>(key, v, lane);
   const bool over = key >= 0 && !(tab && table_add(*tab, key, v));
   outbox_send(ob, over, key, v, lane, g, RR, R);
 }
