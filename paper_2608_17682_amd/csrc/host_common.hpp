@@ -33,7 +33,7 @@ inline WsLayout ws_layout(int32_t n, int64_t m) {
   WsLayout L;
   L.cells = 0;
   L.edges = align256((size_t)n * 32);
-  L.locate = align256(L.edges + ((size_t)m + 3 * (size_t)n) * 16);  // rows padded to 4
+  L.locate = align256(L.edges + (size_t)m * 16);
   L.counters = align256(L.locate + (size_t)kLocateBruteMax * kLocateChunks * 16);
   L.total = align256(L.counters + 4096);
   return L;

@@ -21,9 +21,8 @@ constexpr float kInf = __builtin_huge_valf();
 // (the ints stored by bit pattern).  Edge record, 16 bytes: {m.x, m.y, m.z, j}
 // with m = n / |n|^2, n = p_j - p_i (the quotient formed in FP64 from the FP32
 // positions and rounded once) and j the neighbour id (bit pattern).  Row i
-// starts at edge_off = nbr_off[i] + 3 i and holds deg records followed by
-// null records {0, 0, 0, i} up to a multiple of 4, so an exit search reads
-// whole groups of four consecutive float4s.
+// holds deg consecutive records from edge_off = nbr_off[i]; an exit search
+// reads groups of four, the last 0-3 records under a per-lane mask.
 struct DevScene {
   const float4* __restrict__ cells;
   const float4* __restrict__ edges;
@@ -112,18 +111,31 @@ __device__ __forceinline__ Best exit_search(const float4* __restrict__ edges, in
   r.j1 = -1;
   r.t2 = kInf;
   const float4* e = edges + off;
-  const int deg4 = (deg + 3) & ~3;
   if constexpr (LPR == 1) {
-    for (int k = 0; k < deg4; k += 4) {
+    const int full = deg & ~3;
+    for (int k = 0; k < full; k += 4) {
       const float4 E0 = e[k], E1 = e[k + 1], E2 = e[k + 2], E3 = e[k + 3];
       best_push(r, cross_u(E0, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E0.w));
       best_push(r, cross_u(E1, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E1.w));
       best_push(r, cross_u(E2, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E2.w));
       best_push(r, cross_u(E3, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E3.w));
     }
+    const int rem = deg - full;
+    if (rem > 0) {
+      const float4 E0 = e[full];
+      best_push(r, cross_u(E0, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E0.w));
+      if (rem > 1) {
+        const float4 E1 = e[full + 1];
+        best_push(r, cross_u(E1, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E1.w));
+        if (rem > 2) {
+          const float4 E2 = e[full + 2];
+          best_push(r, cross_u(E2, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E2.w));
+        }
+      }
+    }
   } else {
 #pragma unroll 2
-    for (int k = sub; k < deg4; k += LPR) {
+    for (int k = sub; k < deg; k += LPR) {
       const float4 E = e[k];
       best_push(r, cross_u(E, q2x, q2y, q2z, dx, dy, dz), __float_as_int(E.w));
     }

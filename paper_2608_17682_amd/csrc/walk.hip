@@ -16,9 +16,9 @@ namespace voro {
 
 // ------------------------------------------------------------------ prepare
 // 16 lanes per cell: lane 0 writes the cell record, all 16 stride over the
-// cell's padded row writing edge records (coalesced 256-byte runs).  Row i
-// starts at nbr_off[i] + 3 i, so rows padded to a multiple of 4 never
-// overlap and no scan is needed.
+// cell's row writing edge records (coalesced 256-byte runs).  Rows keep the
+// adjacency's own offsets: compact, so the walk's working set is as small
+// as the adjacency.
 struct PrepArgs {
   const float* sites;
   const float* density;
@@ -40,23 +40,21 @@ __global__ void __launch_bounds__(256) k_prepare(PrepArgs a) {
   const int off = a.nbr_off[i];
   const int end = a.nbr_off[i + 1];
   const bool bad_row = off < 0 || end < off || end > a.m;
-  const int row = off + 3 * i;  // < m + 3 n < 2^31 (checked on the host)
   const int deg = bad_row ? 0 : end - off;
   const float px = a.sites[3 * (size_t)i];
   const float py = a.sites[3 * (size_t)i + 1];
   const float pz = a.sites[3 * (size_t)i + 2];
   if (l16 == 0) {
     a.cells[2 * (size_t)i] = make_float4(px, py, pz, a.density[i]);
-    a.cells[2 * (size_t)i + 1] = make_float4(__int_as_float(bad_row ? 0 : row),
+    a.cells[2 * (size_t)i + 1] = make_float4(__int_as_float(bad_row ? 0 : off),
                                              __int_as_float(deg), 0.0f, 0.0f);
     if (bad_row && a.stats) atomicAdd(&a.stats[VORO_STAT_BAD_CSR], 1ull);
   }
   if (bad_row) return;
-  const int deg4 = (deg + 3) & ~3;
-  for (int e = l16; e < deg4; e += 16) {
+  for (int e = l16; e < deg; e += 16) {
     // null record: m = 0 gives m.w = 0, which no exit search accepts
     float4 E = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(i));
-    if (e < deg) {
+    {
       const int j = a.nbr_idx[off + e];
       if (j < 0 || j >= a.n || j == i) {
         if (a.stats) atomicAdd(&a.stats[VORO_STAT_BAD_CSR], 1ull);
@@ -74,7 +72,7 @@ __global__ void __launch_bounds__(256) k_prepare(PrepArgs a) {
         }
       }
     }
-    a.edges[row + e] = E;
+    a.edges[off + e] = E;
   }
 }
 
