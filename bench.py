@@ -397,6 +397,25 @@ def main():
                           "max_abs_rgb_change": err})
         extras["skip_sweep"] = sweep
         del ref_rgb
+        # half-precision edge vectors for ranking (Sec. 5.6 inference variant):
+        # throughput and agreement with the exact walk over the 8 poses
+        p16 = voro.voro_params.from_buffer_copy(params)
+        p16.edge_fp16 = 1
+        p16.lanes_per_ray = 1
+        s = timed(lambda: step(ds, p16), args.steps, args.warmup)
+        same, dmax, dsum = 0.0, 0.0, 0.0
+        ref = torch.empty((npx, 3), device=dev)
+        for i in range(N_POSES):
+            frame(i, params, ds, out_rgb=ref)
+            frame(i, p16, ds)
+            d = (rgb - ref).abs().max(1).values
+            same += float((d == 0).float().mean()) / N_POSES
+            dmax = max(dmax, float(d.max()))
+            dsum += float(d.mean()) / N_POSES
+        extras["edge_fp16"] = {"fwd_mrays_s": round(rays_per_step * args.steps / s / 1e6, 2),
+                               "pixels_identical_to_exact": round(same, 6),
+                               "max_abs_rgb_diff": dmax, "mean_abs_rgb_diff": dsum}
+        del ref
         # motion blur (Sec. 6.5): 2 views of 960x540 pixels x 5 time samples
         # in one launch, pixel = mean of its samples
         mb = [voro.camera_of(c) for c in synth.motion_blur_cameras(1.0, spp=5)]

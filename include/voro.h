@@ -149,6 +149,12 @@ typedef struct voro_scene {
  *               are walked in index order                               [0]
  *   max_record  cells recorded per ray in voro_render_fwd's `cells`     [0]
  *   block       threads per workgroup: 64, 128 or 256 (0 = 256)          [0]
+ *   edge_fp16   forward-only inference variant (Sec. 5.6 "fp16 edge
+ *               vectors"): neighbours are ranked from half-precision copies
+ *               of the packed edge vectors (two per 16-byte load) and the
+ *               winner's crossing is taken from its full-precision record;
+ *               one lane per ray only.  A ray may take a different exit
+ *               where two faces are within half-precision error.         [0]
  *   schedule    multi-view launches: VORO_SCHEDULE_GRID (one work tile per
  *               wave, hardware dispatch) or VORO_SCHEDULE_PERSISTENT (waves
  *               loop over an XCD-partitioned tile queue); 0 = grid      [0]
@@ -166,7 +172,8 @@ typedef struct voro_params {
   int32_t max_record;
   int32_t block;
   int32_t schedule;
-  int32_t reserved[4]; /* must be 0 */
+  int32_t edge_fp16;
+  int32_t reserved[3]; /* must be 0 */
 } voro_params;
 
 enum { VORO_SCHEDULE_DEFAULT = 0, VORO_SCHEDULE_GRID = 1, VORO_SCHEDULE_PERSISTENT = 2 };

@@ -100,7 +100,13 @@ voro_status check_params(const voro_params* p, bool backward) {
     return fail(VORO_EINVAL, "block must be 0, 64, 128 or 256");
   if (p->schedule < VORO_SCHEDULE_DEFAULT || p->schedule > VORO_SCHEDULE_PERSISTENT)
     return fail(VORO_EINVAL, "unknown schedule %d", p->schedule);
-  for (int i = 0; i < 4; ++i)
+  if (p->edge_fp16 != 0 && p->edge_fp16 != 1)
+    return fail(VORO_EINVAL, "edge_fp16 must be 0 or 1");
+  if (p->edge_fp16 && backward)
+    return fail(VORO_EUNSUPPORTED, "edge_fp16 is a forward-only inference variant");
+  if (p->edge_fp16 && !(p->lanes_per_ray == 0 || p->lanes_per_ray == 1))
+    return fail(VORO_EUNSUPPORTED, "edge_fp16 needs one lane per ray");
+  for (int i = 0; i < 3; ++i)
     if (p->reserved[i] != 0) return fail(VORO_EINVAL, "params.reserved must be 0");
   return VORO_OK;
 }

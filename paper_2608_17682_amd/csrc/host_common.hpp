@@ -21,19 +21,21 @@ voro_status fail(voro_status st, const char* fmt, ...);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Workspace layout: cell records, edge records, nearest-site partials,
+// Workspace layout: cell records, edge records (FP32, then a half copy of the
+// edge vectors), nearest-site partials,
 // persistent-launch counters and per-view start cells.
 constexpr int kLocateBruteMax = 64;    // origins searched by brute force
 constexpr int kLocateChunks = 256;     // max partial results per origin
 struct WsLayout {
-  size_t cells, edges, locate, counters, total;
+  size_t cells, edges, edges16, locate, counters, total;
 };
 
 inline WsLayout ws_layout(int32_t n, int64_t m) {
   WsLayout L;
   L.cells = 0;
   L.edges = align256((size_t)n * 32);
-  L.locate = align256(L.edges + (size_t)m * 16);
+  L.edges16 = align256(L.edges + (size_t)m * 16);
+  L.locate = align256(L.edges16 + (size_t)m * 8 + 16);
   L.counters = align256(L.locate + (size_t)kLocateBruteMax * kLocateChunks * 16);
   L.total = align256(L.counters + 4096);
   return L;

@@ -26,6 +26,7 @@ constexpr float kInf = __builtin_huge_valf();
 struct DevScene {
   const float4* __restrict__ cells;
   const float4* __restrict__ edges;
+  const uint2* __restrict__ edges16;  // {m.x, m.y | m.z, 0} as binary16, same slots
   const void* __restrict__ texels;
   int n;
   int res;
@@ -146,6 +147,58 @@ __device__ __forceinline__ Best exit_search(const float4* __restrict__ edges, in
       const float u2 = __shfl_xor(r.t2, m);
       best_merge(r, u1, k1, u2);
     }
+  }
+  r.t1 *= 0.5f;
+  r.t2 *= 0.5f;
+  return r;
+}
+
+// ---- half-precision ranking (inference variant, Sec. 5.6 "fp16 edge
+// vectors").  The same u from binary16 copies of m; two records per 16-byte
+// load, one 8-byte load first when the row starts on an odd slot.  Returns
+// the best u's slot index (not the neighbour id) in j1, halved values.
+__device__ __forceinline__ float cross_u16(unsigned xy, unsigned z0, float q2x, float q2y,
+                                           float q2z, float dx, float dy, float dz) {
+  const float mx = (float)__builtin_bit_cast(_Float16, (uint16_t)(xy & 0xffffu));
+  const float my = (float)__builtin_bit_cast(_Float16, (uint16_t)(xy >> 16));
+  const float mz = (float)__builtin_bit_cast(_Float16, (uint16_t)(z0 & 0xffffu));
+  const float b = dot3(mx, my, mz, dx, dy, dz);
+  const float a = fmaf(-mz, q2z, fmaf(-my, q2y, fmaf(-mx, q2x, 1.0f)));
+  return b > 0.0f ? a * __builtin_amdgcn_rcpf(b) : kInf;
+}
+
+__device__ __forceinline__ Best exit_search16(const uint2* __restrict__ edges16, int off, int deg,
+                                              float qx, float qy, float qz, float dx, float dy,
+                                              float dz) {
+  const float q2x = 2.0f * qx, q2y = 2.0f * qy, q2z = 2.0f * qz;
+  Best r;
+  r.t1 = kInf;
+  r.j1 = -1;
+  r.t2 = kInf;
+  const uint2* e = edges16 + off;
+  int k = 0;
+  if ((off & 1) && deg > 0) {
+    const uint2 h = e[0];
+    best_push(r, cross_u16(h.x, h.y, q2x, q2y, q2z, dx, dy, dz), 0);
+    k = 1;
+  }
+  for (; k + 4 <= deg; k += 4) {
+    const uint4 A = *reinterpret_cast<const uint4*>(e + k);
+    const uint4 B = *reinterpret_cast<const uint4*>(e + k + 2);
+    best_push(r, cross_u16(A.x, A.y, q2x, q2y, q2z, dx, dy, dz), k);
+    best_push(r, cross_u16(A.z, A.w, q2x, q2y, q2z, dx, dy, dz), k + 1);
+    best_push(r, cross_u16(B.x, B.y, q2x, q2y, q2z, dx, dy, dz), k + 2);
+    best_push(r, cross_u16(B.z, B.w, q2x, q2y, q2z, dx, dy, dz), k + 3);
+  }
+  if (k + 2 <= deg) {
+    const uint4 A = *reinterpret_cast<const uint4*>(e + k);
+    best_push(r, cross_u16(A.x, A.y, q2x, q2y, q2z, dx, dy, dz), k);
+    best_push(r, cross_u16(A.z, A.w, q2x, q2y, q2z, dx, dy, dz), k + 1);
+    k += 2;
+  }
+  if (k < deg) {
+    const uint2 h = e[k];
+    best_push(r, cross_u16(h.x, h.y, q2x, q2y, q2z, dx, dy, dz), k);
   }
   r.t1 *= 0.5f;
   r.t2 *= 0.5f;

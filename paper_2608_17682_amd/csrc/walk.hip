@@ -28,6 +28,7 @@ struct PrepArgs {
   int m;
   float4* cells;
   float4* edges;
+  uint2* edges16;
   unsigned long long* stats;
 };
 
@@ -73,6 +74,14 @@ __global__ void __launch_bounds__(256) k_prepare(PrepArgs a) {
       }
     }
     a.edges[off + e] = E;
+    // half copy (round to nearest even; magnitudes clamped to the f16 range)
+    const _Float16 hx = (_Float16)fminf(fmaxf(E.x, -65504.0f), 65504.0f);
+    const _Float16 hy = (_Float16)fminf(fmaxf(E.y, -65504.0f), 65504.0f);
+    const _Float16 hz = (_Float16)fminf(fmaxf(E.z, -65504.0f), 65504.0f);
+    a.edges16[off + e] =
+        make_uint2((unsigned)__builtin_bit_cast(uint16_t, hx) |
+                       ((unsigned)__builtin_bit_cast(uint16_t, hy) << 16),
+                   (unsigned)__builtin_bit_cast(uint16_t, hz));
   }
 }
 
@@ -250,6 +259,7 @@ DevScene dev_scene(const voro_scene* s, const void* ws) {
   DevScene d;
   d.cells = reinterpret_cast<const float4*>((const char*)ws + L.cells);
   d.edges = reinterpret_cast<const float4*>((const char*)ws + L.edges);
+  d.edges16 = reinterpret_cast<const uint2*>((const char*)ws + L.edges16);
   d.texels = s->texels;
   d.n = s->n_sites;
   d.res = s->tex_res;
@@ -262,6 +272,7 @@ WalkParams walk_params(const voro_params* p) {
   w.skip_w = p->skip_w;
   w.tie_window = p->tie_window;
   w.max_steps = p->max_steps;
+  w.edge16 = p->edge_fp16;
   return w;
 }
 
@@ -333,6 +344,7 @@ voro_status voro_prepare(const voro_scene* scene, void* ws, size_t ws_bytes, uin
   a.m = (int)scene->n_edges;
   a.cells = reinterpret_cast<float4*>((char*)ws + L.cells);
   a.edges = reinterpret_cast<float4*>((char*)ws + L.edges);
+  a.edges16 = reinterpret_cast<uint2*>((char*)ws + L.edges16);
   a.stats = reinterpret_cast<unsigned long long*>(stats);
   const long threads = (long)scene->n_sites * 16;
   const int blocks = (int)((threads + 255) / 256);

@@ -15,6 +15,7 @@ struct WalkParams {
   float skip_w;
   float tie_window;
   int max_steps;
+  int edge16;  // rank neighbours from the half-precision edge vectors
 };
 
 struct RayIn {
@@ -80,7 +81,20 @@ __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w
   const float qx = fmaf(t_in, r.dx, r.ox) - c.px;
   const float qy = fmaf(t_in, r.dy, r.oy) - c.py;
   const float qz = fmaf(t_in, r.dz, r.oz) - c.pz;
-  const Best b = exit_search<LPR>(s.edges, c.off, c.deg, sub, qx, qy, qz, r.dx, r.dy, r.dz);
+  Best b;
+  if (LPR == 1 && w.edge16) {
+    // rank in half precision; the winner's crossing and id come from its
+    // full-precision record, so agreeing decisions give the exact walk's
+    // numbers (near ties still go to the FP64 re-decision)
+    b = exit_search16(s.edges16, c.off, c.deg, qx, qy, qz, r.dx, r.dy, r.dz);
+    if (b.j1 >= 0) {
+      const float4 E = s.edges[c.off + b.j1];
+      b.t1 = 0.5f * cross_u(E, 2.0f * qx, 2.0f * qy, 2.0f * qz, r.dx, r.dy, r.dz);
+      b.j1 = __float_as_int(E.w);
+    }
+  } else {
+    b = exit_search<LPR>(s.edges, c.off, c.deg, sub, qx, qy, qz, r.dx, r.dy, r.dz);
+  }
   return decide_exit(b, s.cells, s.edges, cur, c.off, c.deg, t_in, w.tie_window, r.ox, r.oy, r.oz,
                      r.dx, r.dy, r.dz, qx, qy, qz);
 }

@@ -65,7 +65,7 @@ class voro_params(ctypes.Structure):
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("img_w", ctypes.c_int32), ("max_record", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("edge_fp16", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class voro_camera(ctypes.Structure):

@@ -406,6 +406,43 @@ def test_autograd_distortion(dev, c1):
     assert_grad_close(sites.grad.cpu().numpy(), gs, "sites")
 
 
+def test_edge_fp16_variant_error_is_small_and_reported(dev, c1):
+    # inference variant: half-precision ranking with the winner's crossing from
+    # its FP32 record; most rays repeat the exact walk bit for bit, and the
+    # rest stay close to the oracle
+    p16 = voro.default_params(edge_fp16=1)
+    announce("edge_fp16 variant config1")
+    rgb16, T16 = voro.voro_render_fwd(c1.ds, c1.O, c1.D, c1.TM, c1.S, p16)
+    rgb, T = voro.voro_render_fwd(c1.ds, c1.O, c1.D, c1.TM, c1.S, voro.default_params())
+    same = (rgb16 == rgb).all(1) & (T16 == T)
+    frac = float(same.float().mean())
+    err = np.abs(rgb16.cpu().numpy() - c1.rgb).max(1)
+    print(f"edge_fp16: identical rays {frac:.4f}, max |drgb| vs oracle {err.max():.2e}, "
+          f"mean {err.mean():.2e}")
+    assert frac > 0.97
+    assert err.mean() < 2e-3
+    # views launch: same variant, same result as explicit rays
+    cams = synth.config5_cameras(scale=0.05)[:2]
+    for cm in cams:
+        cm.tmax = 4.0
+    rv, tv, _ = voro.voro_render_views_fwd(c1.ds, cams, p16)
+    O, D, TM = voro.voro_gen_rays(cams, dev)
+    centres = to_dev(f32([cm.c2w[:, 3] for cm in cams]), dev)
+    cc = voro.voro_locate_origins(c1.ds, centres)
+    nr = [cm.n_rays for cm in cams]
+    hint = torch.cat([cc[i:i + 1].expand(n) for i, n in enumerate(nr)]).contiguous()
+    S = voro.voro_locate_origins(c1.ds, O, hint=hint)
+    re_, te = voro.voro_render_fwd(c1.ds, O, D, TM, S, p16)
+    assert torch.equal(rv, re_) and torch.equal(tv, te)
+    # forward only, one lane per ray
+    with pytest.raises(voro.VoroError):
+        voro.voro_render_bwd(c1.ds, c1.O, c1.D, c1.TM, c1.S, rgb16, T16, torch.zeros_like(rgb16),
+                             None, p16)
+    with pytest.raises(voro.VoroError):
+        voro.voro_render_fwd(c1.ds, c1.O, c1.D, c1.TM, c1.S,
+                             voro.default_params(edge_fp16=1, lanes_per_ray=2))
+
+
 @pytest.mark.parametrize("schedule", [voro.SCHEDULE_GRID, voro.SCHEDULE_PERSISTENT])
 def test_autograd_views_equals_explicit(dev, c1, schedule):
     # render_views (in-kernel rays, one launch each way) and render over the
