@@ -308,6 +308,8 @@ __device__ __forceinline__ void table_clear(const GradTable& t) {
   }
 }
 
+// C0: the first term that may be nonzero (texel-only records start at 4)
+template <int C0 = 0>
 __device__ __forceinline__ bool table_add(const GradTable& t, int key, const float* v) {
   const unsigned h = ((unsigned)key * 2654435761u) >> (32 - kTableBits);
   for (int p = 0; p < kTableProbes; ++p) {
@@ -316,7 +318,7 @@ __device__ __forceinline__ bool table_add(const GradTable& t, int key, const flo
     if (k == -1) k = atomicCAS(&t.keys[slot], -1, key);
     if (k == -1 || k == key) {
 #pragma unroll
-      for (int c = 0; c < 16; ++c)
+      for (int c = C0; c < 16; ++c)
         if (v[c] != 0.0f) atomicAdd(&t.vals[c * kTableCap + slot], v[c]);
       return true;
     }
@@ -366,19 +368,20 @@ __device__ __forceinline__ int xor_lane(int x, int lane) {
 }
 
 // One butterfly level: partners holding the same key add up and the upper
-// one retires.  Every lane of the wave must call this.
-template <int M>
+// one retires (terms below C0 are zero by construction and not exchanged).
+// Every lane of the wave must call this.
+template <int M, int C0>
 __device__ __forceinline__ void merge_level(int& key, float (&v)[16], int lane) {
   const int pk = xor_lane<M>(key, lane);
   const bool match = key >= 0 && pk == key;
   if (!__any(match)) return;
   float pv[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) pv[i] = __int_as_float(xor_lane<M>(__float_as_int(v[i]), lane));
+  for (int i = C0; i < 16; ++i) pv[i] = __int_as_float(xor_lane<M>(__float_as_int(v[i]), lane));
   if (match) {
     if ((lane & M) == 0) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] += pv[i];
+      for (int i = C0; i < 16; ++i) v[i] += pv[i];
     } else {
       key = -1;
     }
@@ -389,8 +392,9 @@ __device__ __forceinline__ void merge_level(int& key, float (&v)[16], int lane) 
 // for m = LPR .. 32), then add the survivors to the workgroup table (or, with
 // no table, to global memory).  Every lane of the wave must call this (key <
 // 0: no record).
-// The texel term of tap t and channel ch is tap weight t x m_ch.
-template <int LPR>
+// The texel term of tap t and channel ch is tap weight t x m_ch.  C0 = 4
+// marks a texel-only record (ds and dp are zero and skipped).
+template <int LPR, int C0 = 0>
 __device__ __forceinline__ void emit_records(int key, float ds, float px, float py, float pz,
                                              const Taps& tp, float mr, float mg, float mb, int lane,
                                              int RR, int R, const Grads& g, const GradTable* tab,
@@ -407,13 +411,13 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
     v[5 + 3 * t] = q[t] * mg;
     v[6 + 3 * t] = q[t] * mb;
   }
-  if constexpr (LPR <= 1) merge_level<1>(key, v, lane);
-  if constexpr (LPR <= 2) merge_level<2>(key, v, lane);
-  if constexpr (LPR <= 4) merge_level<4>(key, v, lane);
-  if constexpr (LPR <= 8) merge_level<8>(key, v, lane);
-  if constexpr (LPR <= 16) merge_level<16>(key, v, lane);
-  merge_level<32>(key, v, lane);
-  const bool over = key >= 0 && !(tab && table_add(*tab, key, v));
+  if constexpr (LPR <= 1) merge_level<1, C0>(key, v, lane);
+  if constexpr (LPR <= 2) merge_level<2, C0>(key, v, lane);
+  if constexpr (LPR <= 4) merge_level<4, C0>(key, v, lane);
+  if constexpr (LPR <= 8) merge_level<8, C0>(key, v, lane);
+  if constexpr (LPR <= 16) merge_level<16, C0>(key, v, lane);
+  merge_level<32, C0>(key, v, lane);
+  const bool over = key >= 0 && !(tab && table_add<C0>(*tab, key, v));
   outbox_send(ob, over, key, v, lane, g, RR, R);
 }
 
@@ -674,8 +678,8 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
     emit_records<LPR>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane, RR, R, g, tab,
                       ob);
     if constexpr (APP == 1)
-      emit_records<LPR>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R, g, tab,
-                        ob);
+      emit_records<LPR, 4>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R, g,
+                           tab, ob);
   }
   // the last visited cell, and the unvisited cell behind an early-stopped ray's exit face
   emit_records<LPR>(lead && a_cell >= 0 ? (a_cell * MAPS) * RR + a_tp.base : -1, a_ds, a_px, a_py,
