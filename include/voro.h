@@ -156,8 +156,12 @@ typedef struct voro_scene {
  *               one lane per ray only.  A ray may take a different exit
  *               where two faces are within half-precision error.         [0]
  *   schedule    multi-view launches: VORO_SCHEDULE_GRID (one work tile per
- *               wave, hardware dispatch) or VORO_SCHEDULE_PERSISTENT (waves
- *               loop over an XCD-partitioned tile queue); 0 = grid      [0]
+ *               wave, hardware dispatch), VORO_SCHEDULE_PERSISTENT (waves
+ *               loop over an XCD-partitioned tile queue) or
+ *               VORO_SCHEDULE_REFILL (forward with one lane per ray: a wave
+ *               owns a strip of 4 tiles and refills lanes whose ray ended,
+ *               by ballot, once 16 are idle; the adjoint then uses the
+ *               persistent queue); 0 = grid                            [0]
  */
 typedef struct voro_params {
   float t_stop;
@@ -176,7 +180,12 @@ typedef struct voro_params {
   int32_t reserved[3]; /* must be 0 */
 } voro_params;
 
-enum { VORO_SCHEDULE_DEFAULT = 0, VORO_SCHEDULE_GRID = 1, VORO_SCHEDULE_PERSISTENT = 2 };
+enum {
+  VORO_SCHEDULE_DEFAULT = 0,
+  VORO_SCHEDULE_GRID = 1,
+  VORO_SCHEDULE_PERSISTENT = 2,
+  VORO_SCHEDULE_REFILL = 3
+};
 
 /*
  * A camera (Sec. 6.5 / App. D: only ray generation changes).  c2w is the

@@ -23,7 +23,7 @@ TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table
 
 def candidates() -> List[dict]:
     """Lanes per ray x wave tile (tile_w * tile_h * lanes = 64, aspect <= 8) x workgroup
-    x schedule (1 = grid, 2 = persistent queue)."""
+    x schedule (1 = grid, 2 = persistent queue, 3 = lane refill with one lane per ray)."""
     out = []
     for lpr in (1, 2, 4, 8, 16):
         rays = 64 // lpr
@@ -32,7 +32,7 @@ def candidates() -> List[dict]:
             h = rays // w
             if max(w, h) <= 8 * min(w, h):
                 for block in (128, 256):
-                    for schedule in (1, 2):
+                    for schedule in ((1, 2, 3) if lpr == 1 else (1, 2)):
                         out.append({"lanes_per_ray": lpr, "tile_w": w, "tile_h": h,
                                     "block": block, "schedule": schedule})
             w *= 2

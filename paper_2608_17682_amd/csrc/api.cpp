@@ -98,7 +98,7 @@ voro_status check_params(const voro_params* p, bool backward) {
   if (p->max_record < 0) return fail(VORO_EINVAL, "max_record must be >= 0");
   if (!(p->block == 0 || p->block == 64 || p->block == 128 || p->block == 256))
     return fail(VORO_EINVAL, "block must be 0, 64, 128 or 256");
-  if (p->schedule < VORO_SCHEDULE_DEFAULT || p->schedule > VORO_SCHEDULE_PERSISTENT)
+  if (p->schedule < VORO_SCHEDULE_DEFAULT || p->schedule > VORO_SCHEDULE_REFILL)
     return fail(VORO_EINVAL, "unknown schedule %d", p->schedule);
   if (p->edge_fp16 != 0 && p->edge_fp16 != 1)
     return fail(VORO_EINVAL, "edge_fp16 must be 0 or 1");

@@ -60,6 +60,9 @@ struct ViewsArgs {
   unsigned int* counters;      // [kXcd]
   int total_tiles;
   int tile_w, tile_h;
+  // refill schedule: strips of strip_tiles tiles inside one view
+  int strip_off[VORO_MAX_VIEWS + 1];
+  int strip_tiles;
   // forward
   float* rgb;
   float* T;
@@ -153,6 +156,24 @@ __device__ __forceinline__ RayIn views_ray(const ViewsArgs& a, const TileRay& tr
   return r;
 }
 
+// one ray's forward outputs
+template <int LPR>
+__device__ __forceinline__ void write_ray_out(const ViewsArgs& a, const TileRay& tr,
+                                              const RayOut& out) {
+  const voro_camera& c = a.ct.cam[tr.view];
+  if (c.spp == 1) {
+    const size_t p = (size_t)a.ct.pix_off[tr.view] + tr.pixel;
+    a.rgb[3 * p] = out.r;
+    a.rgb[3 * p + 1] = out.g;
+    a.rgb[3 * p + 2] = out.b;
+    a.T[p] = out.T;
+  }
+  if (a.ray_rgbT) {
+    reinterpret_cast<float4*>(a.ray_rgbT)[tr.ray] = make_float4(out.r, out.g, out.b, out.T);
+  }
+  if (a.nsteps) a.nsteps[tr.ray] = out.k;
+}
+
 // PERSIST: waves loop over the XCD-partitioned tile queue; otherwise each
 // wave of the grid takes one tile (workgroups renumbered per XCD) and the
 // hardware dispatcher balances the load.
@@ -180,26 +201,72 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
       const RayIn r = views_ray(a, tr, &capped);
       capped_n += capped ? 1u : 0u;
       const RayOut out = walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, nullptr, 0, cnt);
-      if (sub == 0) {
-        const voro_camera& c = a.ct.cam[tr.view];
-        if (c.spp == 1) {
-          const size_t p = (size_t)a.ct.pix_off[tr.view] + tr.pixel;
-          a.rgb[3 * p] = out.r;
-          a.rgb[3 * p + 1] = out.g;
-          a.rgb[3 * p + 2] = out.b;
-          a.T[p] = out.T;
-        }
-        if (a.ray_rgbT) {
-          reinterpret_cast<float4*>(a.ray_rgbT)[tr.ray] = make_float4(out.r, out.g, out.b, out.T);
-        }
-        if (a.nsteps) a.nsteps[tr.ray] = out.k;
-      }
+      if (sub == 0) write_ray_out<LPR>(a, tr, out);
     }
     if constexpr (!PERSIST) break;
   }
   if (a.stats) {
     flush_counters(cnt, sub == 0, lane, a.stats);
     const uint32_t cp = wave_sum_u32(sub == 0 ? capped_n : 0u);
+    if (lane == 0 && cp) atomicAdd(&a.stats[VORO_STAT_LOCATE_CAP], (unsigned long long)cp);
+  }
+}
+
+// Refill schedule (one lane per ray): each wave owns a strip of tiles in one
+// view and keeps its lanes busy across the strip: whenever at least
+// kRefillMin lanes (or all of them) have finished their rays, the idle lanes
+// take the strip's next rays in lane order (ballot + rank) and the walk goes
+// on.  Every refill advances the strip cursor by the idle count and every
+// ray ends within max_steps, so the loop ends.
+constexpr int kRefillMin = 16;
+constexpr int kStripTiles = 4;  // 256 rays per wave
+
+template <int TEX, int APP>
+__global__ void __launch_bounds__(256) k_views_fwd_refill(ViewsArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  Counters cnt;
+  uint32_t capped_n = 0;
+  const int strip = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
+  if (strip < a.strip_off[a.ct.V]) {
+    const int v = find_view(a.strip_off, a.ct.V, strip);
+    const int t0 = a.ct.tile_off[v] + (strip - a.strip_off[v]) * a.strip_tiles;
+    const int nt = min(a.strip_tiles, a.ct.tile_off[v + 1] - t0);
+    const int pool = nt * 64;
+    int q = 0;  // next ray of the strip (wave-uniform)
+    bool active = false;
+    FwdState<APP> st;
+    RayIn r = {};
+    TileRay tr = {};
+    for (;;) {
+      const unsigned long long idle = __ballot(!active);
+      const int n_idle = __popcll(idle);
+      if (q < pool && (n_idle >= kRefillMin || n_idle == 64)) {
+        const int idx = q + __popcll(idle & ((1ull << lane) - 1ull));
+        if (!active && idx < pool &&
+            tile_ray(a.ct, t0 + (idx >> 6), 0, 0, idx & 63, a.tile_w, a.tile_h, a.tile_w,
+                     a.tile_h, tr)) {
+          bool capped = false;
+          r = views_ray(a, tr, &capped);
+          capped_n += capped ? 1u : 0u;
+          active = fwd_begin<APP>(st, a.s, r, cnt);
+          if (!active) write_ray_out<1>(a, tr, fwd_end<APP>(st, false, cnt));
+        }
+        q += n_idle;
+      }
+      if (!__any(active)) {
+        if (q >= pool) break;
+        continue;
+      }
+      if (active && fwd_step<1, TEX, APP>(st, a.s, a.w, r, 0, nullptr, 0, cnt, false)) {
+        write_ray_out<1>(a, tr, fwd_end<APP>(st, true, cnt));
+        active = false;
+      }
+    }
+  }
+  if (a.stats) {
+    flush_counters(cnt, true, lane, a.stats);
+    const uint32_t cp = wave_sum_u32(capped_n);
     if (lane == 0 && cp) atomicAdd(&a.stats[VORO_STAT_LOCATE_CAP], (unsigned long long)cp);
   }
 }
@@ -361,6 +428,14 @@ template <int LPR, int TEX, int APP>
 static void launch_views_t(bool backward, bool persist, const ViewsArgs& a, int block,
                            hipStream_t st) {
   const int nwaves = block / 64;
+  if constexpr (LPR == 1) {
+    if (!backward && a.strip_tiles > 0) {
+      const int strips = a.strip_off[a.ct.V];
+      hipLaunchKernelGGL((k_views_fwd_refill<TEX, APP>), dim3(max(1, (strips + nwaves - 1) / nwaves)),
+                         dim3(block), 0, st, a);
+      return;
+    }
+  }
   if constexpr (APP == 2) {
     // forward only: the comparison model has no adjoint (refused on the host)
     if (persist) {
@@ -450,7 +525,21 @@ static voro_status views_common(bool backward, const voro_scene* scene, void* ws
   if ((st = check_launch("views: setup")) != VORO_OK) return st;
   if ((st = launch_locate_brute(scene, ws, origins, V, centers, s)) != VORO_OK) return st;
   const int block = L.block;
-  const bool persist = params->schedule == VORO_SCHEDULE_PERSISTENT;
+  // the refill schedule drives the one-lane-per-ray forward; the adjoint
+  // (whose work unit is a workgroup tile) takes the persistent queue then
+  const bool refill = params->schedule == VORO_SCHEDULE_REFILL;
+  const bool persist = params->schedule == VORO_SCHEDULE_PERSISTENT || (refill && backward);
+  a.strip_tiles = 0;
+  if (refill && !backward && L.lpr == 1) {
+    a.strip_tiles = kStripTiles;
+    int so = 0;
+    for (int v = 0; v < V; ++v) {
+      a.strip_off[v] = so;
+      const int tiles = a.ct.tile_off[v + 1] - a.ct.tile_off[v];
+      so += (tiles + kStripTiles - 1) / kStripTiles;
+    }
+    for (int v = V; v <= VORO_MAX_VIEWS; ++v) a.strip_off[v] = so;
+  }
   if (params->appearance == 1)
     launch_views_tex<1>(scene->tex_dtype, L.lpr, backward, persist, a, block, s);
   else if (params->appearance == 2)

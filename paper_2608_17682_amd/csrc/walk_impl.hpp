@@ -117,93 +117,129 @@ __device__ __forceinline__ Taps ray_taps(const RayIn& r, int R) {
   return APP ? make_taps(-r.dx, -r.dy, -r.dz, R) : make_taps(r.dx, r.dy, r.dz, R);
 }
 
+// Forward walk state of one ray, so that a lane can hold a ray across the
+// steps of a loop it shares with other rays (fwd_begin, fwd_step, fwd_end).
+template <int APP>
+struct FwdState {
+  Taps tp;
+  float Ysh[APP == 2 ? 16 : 1];
+  float T, Cr, Cg, Cb, t_in;
+  float dP, dQ, dW, dA, s0;
+  int cur, k;
+};
+
+// false: nothing to walk (tmax <= 0 or an invalid start cell)
+template <int APP>
+__device__ __forceinline__ bool fwd_begin(FwdState<APP>& st, const DevScene& s, const RayIn& r,
+                                          Counters& cnt) {
+  st.T = 1.0f;
+  st.Cr = st.Cg = st.Cb = 0.0f;
+  st.t_in = 0.0f;
+  st.dP = st.dQ = st.dW = st.dA = st.s0 = 0.0f;
+  st.k = 0;
+  st.cur = r.start;
+  if (!(r.tmax > 0.0f)) return false;
+  if (r.start < 0 || r.start >= s.n) {
+    cnt.bad++;
+    return false;
+  }
+  cnt.rays++;
+  st.tp = ray_taps<APP>(r, s.res);
+  if constexpr (APP == 2) sh3_basis(r.dx, r.dy, r.dz, st.Ysh);
+  return true;
+}
+
+// One visited cell; true when the ray has ended.
+template <int LPR, int TEX, int APP>
+__device__ __forceinline__ bool fwd_step(FwdState<APP>& st, const DevScene& s,
+                                         const WalkParams& w, const RayIn& r, int sub,
+                                         int32_t* rec, int max_record, Counters& cnt,
+                                         bool dist_on) {
+  const int cur = st.cur;
+  const float t_in = st.t_in;
+  const Cell c = load_cell(s.cells, cur);
+  const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
+  cnt.redecide += ex.redecided ? 1u : 0u;
+  cnt.deg += (uint32_t)c.deg;
+  const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
+  const float wk = st.T * sg.alpha;
+  if (dist_on) {
+    const float s1 = dist_s(fmaxf(t_in, fminf(ex.t, r.tmax)));
+    const float sb = 0.5f * (st.s0 + s1);
+    st.dP = fmaf(2.0f * wk, fmaf(sb, st.dW, -st.dA), st.dP);
+    st.dQ = fmaf(wk * wk, s1 - st.s0, st.dQ);
+    st.dW += wk;
+    st.dA = fmaf(wk, sb, st.dA);
+    st.s0 = s1;
+  }
+  if (wk >= w.skip_w) {
+    float cr, cg, cb;
+    if constexpr (APP == 0) {
+      texel_rgb<TEX>(s.texels, cur, s.res, st.tp, cr, cg, cb);
+    } else if constexpr (APP == 2) {
+      sh3_colour<TEX>(s.texels, cur, st.Ysh, cr, cg, cb);
+    } else {
+      float hx, hy, hz;
+      hit_vector(r, c, st.k, t_in, ex.t, hx, hy, hz);
+      const bool on_site = hx == 0.0f && hy == 0.0f && hz == 0.0f;
+      const Taps ts = make_taps(on_site ? r.dx : hx, on_site ? r.dy : hy,
+                                on_site ? r.dz : hz, s.res);
+      float lr, lg, lb;
+      float4 ta, tb, te, tf;
+      full_logits<TEX>(s.texels, cur, s.res, ts, st.tp, lr, lg, lb, ta, tb, te, tf);
+      cr = sigmoid_f(lr);
+      cg = sigmoid_f(lg);
+      cb = sigmoid_f(lb);
+    }
+    st.Cr = fmaf(wk, cr, st.Cr);
+    st.Cg = fmaf(wk, cg, st.Cg);
+    st.Cb = fmaf(wk, cb, st.Cb);
+  } else {
+    cnt.skipped++;
+  }
+  st.T = st.T * sg.trans;
+  if (rec && sub == 0 && st.k < max_record) rec[st.k] = cur;
+  ++st.k;
+  if (st.T < w.t_stop) return true;
+  if (!(ex.t < r.tmax) || ex.next < 0) return true;
+  if (st.k >= w.max_steps) {
+    cnt.maxsteps++;
+    return true;
+  }
+  st.t_in = fmaxf(t_in, fminf(ex.t, r.tmax));
+  st.cur = ex.next;
+  return false;
+}
+
+template <int APP>
+__device__ __forceinline__ RayOut fwd_end(const FwdState<APP>& st, bool walked, Counters& cnt) {
+  RayOut out;
+  out.r = st.Cr;
+  out.g = st.Cg;
+  out.b = st.Cb;
+  out.T = st.T;
+  out.k = st.k;
+  out.dist = fmaf(st.dQ, 1.0f / 3.0f, st.dP);
+  out.dist_a = st.dA;
+  out.dist_w = st.dW;
+  if (walked) {
+    cnt.steps += (uint32_t)st.k;
+    if (st.T != st.T) cnt.nan++;
+  }
+  return out;
+}
+
 template <int LPR, int TEX, int APP>
 __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkParams& w,
                                                const RayIn& r, int sub, int32_t* rec,
                                                int max_record, Counters& cnt,
                                                bool dist_on = false) {
-  RayOut out;
-  out.r = out.g = out.b = 0.0f;
-  out.T = 1.0f;
-  out.k = 0;
-  out.dist = out.dist_a = out.dist_w = 0.0f;
-  if (!(r.tmax > 0.0f)) return out;
-  if (r.start < 0 || r.start >= s.n) {
-    cnt.bad++;
-    return out;
-  }
-  cnt.rays++;
-  const Taps tp = ray_taps<APP>(r, s.res);
-  float Ysh[16];
-  if constexpr (APP == 2) sh3_basis(r.dx, r.dy, r.dz, Ysh);
-  float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, t_in = 0.0f;
-  float dP = 0.0f, dQ = 0.0f, dW = 0.0f, dA = 0.0f, s0 = 0.0f;
-  int cur = r.start;
-  int k = 0;
-  for (;;) {
-    const Cell c = load_cell(s.cells, cur);
-    const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
-    cnt.redecide += ex.redecided ? 1u : 0u;
-    cnt.deg += (uint32_t)c.deg;
-    const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
-    const float wk = T * sg.alpha;
-    if (dist_on) {
-      const float s1 = dist_s(fmaxf(t_in, fminf(ex.t, r.tmax)));
-      const float sb = 0.5f * (s0 + s1);
-      dP = fmaf(2.0f * wk, fmaf(sb, dW, -dA), dP);
-      dQ = fmaf(wk * wk, s1 - s0, dQ);
-      dW += wk;
-      dA = fmaf(wk, sb, dA);
-      s0 = s1;
+  FwdState<APP> st;
+  const bool walk = fwd_begin<APP>(st, s, r, cnt);
+  if (walk)
+    while (!fwd_step<LPR, TEX, APP>(st, s, w, r, sub, rec, max_record, cnt, dist_on)) {
     }
-    if (wk >= w.skip_w) {
-      float cr, cg, cb;
-      if constexpr (APP == 0) {
-        texel_rgb<TEX>(s.texels, cur, s.res, tp, cr, cg, cb);
-      } else if constexpr (APP == 2) {
-        sh3_colour<TEX>(s.texels, cur, Ysh, cr, cg, cb);
-      } else {
-        float hx, hy, hz;
-        hit_vector(r, c, k, t_in, ex.t, hx, hy, hz);
-        const bool on_site = hx == 0.0f && hy == 0.0f && hz == 0.0f;
-        const Taps ts = make_taps(on_site ? r.dx : hx, on_site ? r.dy : hy,
-                                  on_site ? r.dz : hz, s.res);
-        float lr, lg, lb;
-        float4 ta, tb, te, tf;
-        full_logits<TEX>(s.texels, cur, s.res, ts, tp, lr, lg, lb, ta, tb, te, tf);
-        cr = sigmoid_f(lr);
-        cg = sigmoid_f(lg);
-        cb = sigmoid_f(lb);
-      }
-      Cr = fmaf(wk, cr, Cr);
-      Cg = fmaf(wk, cg, Cg);
-      Cb = fmaf(wk, cb, Cb);
-    } else {
-      cnt.skipped++;
-    }
-    T = T * sg.trans;
-    if (rec && sub == 0 && k < max_record) rec[k] = cur;
-    ++k;
-    if (T < w.t_stop) break;
-    if (!(ex.t < r.tmax) || ex.next < 0) break;
-    if (k >= w.max_steps) {
-      cnt.maxsteps++;
-      break;
-    }
-    t_in = fmaxf(t_in, fminf(ex.t, r.tmax));
-    cur = ex.next;
-  }
-  cnt.steps += (uint32_t)k;
-  if (T != T) cnt.nan++;
-  out.r = Cr;
-  out.g = Cg;
-  out.b = Cb;
-  out.T = T;
-  out.k = k;
-  out.dist = fmaf(dQ, 1.0f / 3.0f, dP);
-  out.dist_a = dA;
-  out.dist_w = dW;
-  return out;
+  return fwd_end<APP>(st, walk, cnt);
 }
 
 // ------------------------------------------------------------- adjoint

@@ -28,7 +28,7 @@ VORO_EWORKSPACE = -5
 
 TEX_F32, TEX_F16, TEX_BF16 = 0, 1, 2
 CAM_PINHOLE, CAM_FISHEYE, CAM_ROLLING_SHUTTER, CAM_THIN_LENS, CAM_MOTION_BLUR = 0, 1, 2, 3, 4
-SCHEDULE_DEFAULT, SCHEDULE_GRID, SCHEDULE_PERSISTENT = 0, 1, 2
+SCHEDULE_DEFAULT, SCHEDULE_GRID, SCHEDULE_PERSISTENT, SCHEDULE_REFILL = 0, 1, 2, 3
 MAX_VIEWS = 16
 
 STAT_NAMES = ["rays", "steps", "degree_sum", "max_steps", "nan", "bad_start", "fp64_redecide",

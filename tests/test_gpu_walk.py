@@ -255,14 +255,16 @@ def test_autograd_function(dev, c1):
     assert_grad_close(tex.grad.cpu().numpy(), gt, "texels")
 
 
-def test_views_fwd_equals_explicit_rays(dev, c1):
-    # the persistent multi-view launch generates the same rays, starts in the
-    # same cells and takes the same walk as gen_rays + locate + render_fwd
+@pytest.mark.parametrize("lpr,schedule", [(2, voro.SCHEDULE_GRID), (1, voro.SCHEDULE_REFILL),
+                                          (1, voro.SCHEDULE_PERSISTENT)])
+def test_views_fwd_equals_explicit_rays(dev, c1, lpr, schedule):
+    # every multi-view schedule generates the same rays, starts in the same
+    # cells and takes the same walk as gen_rays + locate + render_fwd
     cams = synth.config5_cameras(scale=0.06) + synth.motion_blur_cameras(scale=0.05)
     for cm in cams:
         cm.tmax = 4.0
-    announce("views fwd vs explicit, 8 mixed cameras")
-    p = voro.default_params(lanes_per_ray=2)
+    announce(f"views fwd vs explicit, mixed cameras, lpr {lpr} schedule {schedule}")
+    p = voro.default_params(lanes_per_ray=lpr, schedule=schedule)
     rgb_v, T_v, ray_v = voro.voro_render_views_fwd(c1.ds, cams, p)
     O, D, TM = voro.voro_gen_rays(cams, dev)
     centres = to_dev(f32([cm.c2w[:, 3] for cm in cams]), dev)
