@@ -176,9 +176,12 @@ __device__ __forceinline__ void write_ray_out(const ViewsArgs& a, const TileRay&
 
 // PERSIST: waves loop over the XCD-partitioned tile queue; otherwise each
 // wave of the grid takes one tile (workgroups renumbered per XCD) and the
-// hardware dispatcher balances the load.
+// hardware dispatcher balances the load.  One lane per ray walks with staged
+// edge rows (dynamic LDS: kStageBytesPerWave per wave) unless the edges are
+// ranked in half precision.
 template <int LPR, int TEX, int APP, bool PERSIST>
 __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
+  extern __shared__ float4 slabs[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int grp = lane / LPR;
@@ -196,7 +199,18 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
       break;
     }
     TileRay tr;
-    if (tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr)) {
+    if (LPR == 1 && !a.w.edge16) {
+      const bool has = tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr);
+      RayIn r{};
+      if (has) {
+        bool capped = false;
+        r = views_ray(a, tr, &capped);
+        capped_n += capped ? 1u : 0u;
+      }
+      const RayOut out = walk_forward_staged<TEX, APP>(
+          a.s, a.w, r, has, lane, slabs + wave * (kStageBytesPerWave / 16), nullptr, 0, cnt);
+      if (has) write_ray_out<LPR>(a, tr, out);
+    } else if (tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr)) {
       bool capped = false;
       const RayIn r = views_ray(a, tr, &capped);
       capped_n += capped ? 1u : 0u;
@@ -402,6 +416,12 @@ static CamTable make_table(const voro_camera* cams, int V, int tile_w, int tile_
   return ct;
 }
 
+// dynamic LDS of a forward launch: the staged edge rows of each wave
+template <int LPR>
+static size_t fwd_lds(int block) {
+  return LPR == 1 ? (size_t)(block / 64) * kStageBytesPerWave : 0;
+}
+
 template <int LPR, int TEX, int APP>
 static int persistent_blocks(bool backward, int block) {
   static int cached[2][3] = {};
@@ -412,11 +432,13 @@ static int persistent_blocks(bool backward, int block) {
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if constexpr (APP == 2) {
     (void)backward;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block,
+                                                       fwd_lds<LPR>(block));
   } else if (backward) {
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX, APP, true>, block, 0);
   } else {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block,
+                                                       fwd_lds<LPR>(block));
   }
   (void)hipGetLastError();
   c = max(kXcd, max(1, cus) * max(1, occ));
@@ -440,23 +462,27 @@ static void launch_views_t(bool backward, bool persist, const ViewsArgs& a, int 
     // forward only: the comparison model has no adjoint (refused on the host)
     if (persist) {
       const int blocks = persistent_blocks<LPR, TEX, APP>(false, block);
-      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
+      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block),
+                         fwd_lds<LPR>(block), st, a);
     } else {
       const int blocks = max(1, (a.total_tiles + nwaves - 1) / nwaves);
-      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block), 0, st, a);
+      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block),
+                         fwd_lds<LPR>(block), st, a);
     }
   } else if (persist) {
     const int blocks = persistent_blocks<LPR, TEX, APP>(backward, block);
     if (backward)
       hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
     else
-      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
+      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block),
+                         fwd_lds<LPR>(block), st, a);
   } else if (backward) {
     hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, false>), dim3(max(1, a.total_tiles)), dim3(block),
                        0, st, a);
   } else {
     const int blocks = max(1, (a.total_tiles + nwaves - 1) / nwaves);
-    hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block),
+                       fwd_lds<LPR>(block), st, a);
   }
 }
 

@@ -112,8 +112,11 @@ struct RayArgs {
   unsigned long long* stats;
 };
 
+// One lane per ray walks with staged edge rows (dynamic LDS:
+// kStageBytesPerWave per wave) unless the edges are ranked in half precision.
 template <int LPR, int TEX, int APP>
 __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
+  extern __shared__ float4 slabs[];
   const int nwaves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -122,21 +125,29 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int ray = map_ray<LPR>(a.map, lb, wave, nwaves, grp);
   Counters cnt;
-  if (ray >= 0) {
-    RayIn r;
-    r.ox = a.o[3 * (size_t)ray];
-    r.oy = a.o[3 * (size_t)ray + 1];
-    r.oz = a.o[3 * (size_t)ray + 2];
-    r.dx = a.d[3 * (size_t)ray];
-    r.dy = a.d[3 * (size_t)ray + 1];
-    r.dz = a.d[3 * (size_t)ray + 2];
-    r.tmax = a.tmax[ray];
-    r.start = a.start[ray];
-    int32_t* rec = (a.cells_out && a.max_record > 0) ? a.cells_out + (size_t)ray * a.max_record
-                                                     : nullptr;
+  const bool staged = LPR == 1 && !a.w.edge16;
+  if (ray >= 0 || staged) {
+    RayIn r{};
+    if (ray >= 0) {
+      r.ox = a.o[3 * (size_t)ray];
+      r.oy = a.o[3 * (size_t)ray + 1];
+      r.oz = a.o[3 * (size_t)ray + 2];
+      r.dx = a.d[3 * (size_t)ray];
+      r.dy = a.d[3 * (size_t)ray + 1];
+      r.dz = a.d[3 * (size_t)ray + 2];
+      r.tmax = a.tmax[ray];
+      r.start = a.start[ray];
+    }
+    int32_t* rec = (ray >= 0 && a.cells_out && a.max_record > 0)
+                       ? a.cells_out + (size_t)ray * a.max_record
+                       : nullptr;
     const RayOut out =
-        walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, rec, a.max_record, cnt, a.dist_out != nullptr);
-    if (sub == 0) {
+        staged ? walk_forward_staged<TEX, APP>(a.s, a.w, r, ray >= 0, lane,
+                                               slabs + wave * (kStageBytesPerWave / 16), rec,
+                                               a.max_record, cnt, a.dist_out != nullptr)
+               : walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, rec, a.max_record, cnt,
+                                             a.dist_out != nullptr);
+    if (ray >= 0 && sub == 0) {
       a.rgb[3 * (size_t)ray] = out.r;
       a.rgb[3 * (size_t)ray + 1] = out.g;
       a.rgb[3 * (size_t)ray + 2] = out.b;
@@ -214,11 +225,13 @@ static void launch_ray_kernel(bool backward, const RayArgs& a, int blocks, int b
                               hipStream_t st) {
   if constexpr (APP == 2) {
     // the spherical-harmonic comparison model has no adjoint (refused on the host)
-    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block),
+                       LPR == 1 ? (size_t)(block / 64) * kStageBytesPerWave : 0, st, a);
   } else if (backward) {
     hipLaunchKernelGGL((k_render_bwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block),
+                       LPR == 1 ? (size_t)(block / 64) * kStageBytesPerWave : 0, st, a);
   }
 }
 

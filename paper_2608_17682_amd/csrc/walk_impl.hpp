@@ -74,10 +74,13 @@ __device__ __forceinline__ void flush_counters(Counters c, bool contribute, int 
   }
 }
 
-// One step of the walk: the exit of cell `cur` entered at t_in.
+// One step of the walk: the exit of cell `cur` entered at t_in.  lrow: the
+// cell's edge row staged in LDS by the wave (one lane per ray), or null to
+// gather it from global memory.
 template <int LPR>
 __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w, const RayIn& r,
-                                          const Cell& c, int cur, float t_in, int sub) {
+                                          const Cell& c, int cur, float t_in, int sub,
+                                          const float4* lrow = nullptr) {
   const float qx = fmaf(t_in, r.dx, r.ox) - c.px;
   const float qy = fmaf(t_in, r.dy, r.oy) - c.py;
   const float qz = fmaf(t_in, r.dz, r.oz) - c.pz;
@@ -92,6 +95,8 @@ __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w
       b.t1 = 0.5f * cross_u(E, 2.0f * qx, 2.0f * qy, 2.0f * qz, r.dx, r.dy, r.dz);
       b.j1 = __float_as_int(E.w);
     }
+  } else if (LPR == 1 && lrow) {
+    b = exit_search<1>(lrow, 0, c.deg, 0, qx, qy, qz, r.dx, r.dy, r.dz);
   } else {
     b = exit_search<LPR>(s.edges, c.off, c.deg, sub, qx, qy, qz, r.dx, r.dy, r.dz);
   }
@@ -149,16 +154,17 @@ __device__ __forceinline__ bool fwd_begin(FwdState<APP>& st, const DevScene& s, 
   return true;
 }
 
-// One visited cell; true when the ray has ended.
+// One visited cell (lrow: its edge row staged in LDS, or null); true when
+// the ray has ended.
 template <int LPR, int TEX, int APP>
 __device__ __forceinline__ bool fwd_step(FwdState<APP>& st, const DevScene& s,
                                          const WalkParams& w, const RayIn& r, int sub,
                                          int32_t* rec, int max_record, Counters& cnt,
-                                         bool dist_on) {
+                                         bool dist_on, const float4* lrow = nullptr) {
   const int cur = st.cur;
   const float t_in = st.t_in;
   const Cell c = load_cell(s.cells, cur);
-  const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
+  const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub, lrow);
   cnt.redecide += ex.redecided ? 1u : 0u;
   cnt.deg += (uint32_t)c.deg;
   const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
@@ -239,6 +245,83 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
   if (walk)
     while (!fwd_step<LPR, TEX, APP>(st, s, w, r, sub, rec, max_record, cnt, dist_on)) {
     }
+  return fwd_end<APP>(st, walk, cnt);
+}
+
+// Wave-cooperative staging of edge rows (one lane per ray).  Rays of a
+// coherent tile often stand in the same few cells: when the live lanes of
+// the wave sit in at most kStageCells distinct cells whose rows (at most 64
+// faces each) fit the wave's LDS slab together, the wave copies those rows
+// into the slab, one coalesced load per row, and every live lane reads its
+// row from there; otherwise each lane gathers its own row from global
+// memory.  The choice is per wave and step (mixing both within one step was
+// slower: the two loops then run one after the other), and the exit search
+// sees the same records in the same order either way.
+constexpr int kStageCells = 8;
+constexpr int kStageRecords = 256;
+constexpr int kStageBytesPerWave = kStageRecords * 16;
+
+// Every lane of the wave must call this; alive: the lane's walk goes on, at
+// cell cur with record c.  Returns the lane's staged row or null.
+__device__ __forceinline__ const float4* stage_rows(const float4* __restrict__ edges, float4* slab,
+                                                    bool alive, int cur, const Cell& c, int lane) {
+  unsigned long long pend = __ballot(alive);
+  int mine = 0;
+  int offs[kStageCells], degs[kStageCells];
+  int n = 0, used = 0;
+  bool fits = true;
+#pragma unroll
+  for (int q = 0; q < kStageCells; ++q) {
+    if (pend == 0ull) break;
+    const int leader = __ffsll((long long)pend) - 1;  // wave-uniform
+    const int cl = __builtin_amdgcn_readlane(cur, leader);
+    offs[q] = __builtin_amdgcn_readlane(c.off, leader);
+    degs[q] = __builtin_amdgcn_readlane(c.deg, leader);
+    const bool same = alive && cur == cl;
+    pend &= ~__ballot(same);
+    if (same) mine = used;
+    fits = fits && degs[q] <= 64;
+    used += degs[q];
+    n = q + 1;
+  }
+  if (pend != 0ull || !fits || used > kStageRecords) return nullptr;
+  // the slab's previous rows have been read by every lane (LDS operations of
+  // one wave complete in order)
+  __builtin_amdgcn_wave_barrier();
+  int base = 0;
+#pragma unroll
+  for (int q = 0; q < kStageCells; ++q) {
+    if (q < n && lane < degs[q]) slab[base + lane] = edges[offs[q] + lane];
+    base += q < n ? degs[q] : 0;
+  }
+  __builtin_amdgcn_wave_barrier();
+  return slab + mine;
+}
+
+// walk_forward with one lane per ray and staged rows.  Every lane of the
+// wave must call this (has_ray = false for lanes without a ray); slab: the
+// wave's kStageBytesPerWave of LDS.
+template <int TEX, int APP>
+__device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const WalkParams& w,
+                                                      const RayIn& r, bool has_ray, int lane,
+                                                      float4* slab, int32_t* rec, int max_record,
+                                                      Counters& cnt, bool dist_on = false) {
+  FwdState<APP> st;
+  const bool walk = has_ray && fwd_begin<APP>(st, s, r, cnt);
+  bool alive = walk;
+  while (__any(alive)) {
+    // the row bounds for the staging; fwd_step takes the record again (the
+    // compiler keeps one load)
+    Cell c;
+    if (alive) c = load_cell(s.cells, st.cur);
+    const float4* row = stage_rows(s.edges, slab, alive, st.cur, c, lane);
+    if (alive) {
+      if (row)
+        alive = !fwd_step<1, TEX, APP>(st, s, w, r, 0, rec, max_record, cnt, dist_on, row);
+      else
+        alive = !fwd_step<1, TEX, APP>(st, s, w, r, 0, rec, max_record, cnt, dist_on);
+    }
+  }
   return fwd_end<APP>(st, walk, cnt);
 }
 
