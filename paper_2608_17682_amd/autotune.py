@@ -101,6 +101,8 @@ def tune(ds, cams, reps: int = 3, cands: Iterable[dict] = None, log=print) -> Di
     for direction in ("fwd", "bwd"):
         res = []
         for c in cands:
+            if direction == "bwd" and c["schedule"] == 3:
+                continue  # the adjoint has no refill kernel: it runs the persistent queue
             p = voro.default_params(**c)
             if direction == "fwd":
                 fn = lambda: voro.voro_render_views_fwd(ds, arr, p, rgb, T, ray)  # noqa: E731

@@ -260,11 +260,14 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
 constexpr int kStageCells = 8;
 constexpr int kStageRecords = 256;
 constexpr int kStageBytesPerWave = kStageRecords * 16;
+constexpr int kStageMaxGap = 8;
 
 // Every lane of the wave must call this; alive: the lane's walk goes on, at
-// cell cur with record c.  Returns the lane's staged row or null.
+// cell cur with record c.  Returns the lane's staged row, or null when the
+// wave's rows were not staged (then staged = false on every lane).
 __device__ __forceinline__ const float4* stage_rows(const float4* __restrict__ edges, float4* slab,
-                                                    bool alive, int cur, const Cell& c, int lane) {
+                                                    bool alive, int cur, const Cell& c, int lane,
+                                                    bool& staged) {
   unsigned long long pend = __ballot(alive);
   int mine = 0;
   int offs[kStageCells], degs[kStageCells];
@@ -284,7 +287,8 @@ __device__ __forceinline__ const float4* stage_rows(const float4* __restrict__ e
     used += degs[q];
     n = q + 1;
   }
-  if (pend != 0ull || !fits || used > kStageRecords) return nullptr;
+  staged = pend == 0ull && fits && used <= kStageRecords;
+  if (!staged) return nullptr;
   // the slab's previous rows have been read by every lane (LDS operations of
   // one wave complete in order)
   __builtin_amdgcn_wave_barrier();
@@ -309,12 +313,29 @@ __device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const W
   FwdState<APP> st;
   const bool walk = has_ray && fwd_begin<APP>(st, s, r, cnt);
   bool alive = walk;
+  // after a step whose rows could not be staged the wave waits `wait` steps
+  // before it tries again, doubling the wait up to kStageMaxGap while it
+  // keeps failing (rays that have spread apart seldom meet again soon, and
+  // each failed try costs a full pass over kStageCells ballots)
+  int wait = 0, gap = 1;
   while (__any(alive)) {
-    // the row bounds for the staging; fwd_step takes the record again (the
-    // compiler keeps one load)
-    Cell c;
-    if (alive) c = load_cell(s.cells, st.cur);
-    const float4* row = stage_rows(s.edges, slab, alive, st.cur, c, lane);
+    const float4* row = nullptr;
+    if (wait == 0) {
+      // the row bounds for the staging; fwd_step takes the record again
+      // (the compiler keeps one load)
+      Cell c;
+      if (alive) c = load_cell(s.cells, st.cur);
+      bool staged;
+      row = stage_rows(s.edges, slab, alive, st.cur, c, lane, staged);
+      if (staged) {
+        gap = 1;
+      } else {
+        wait = gap;
+        gap = min(2 * gap, kStageMaxGap);
+      }
+    } else {
+      --wait;
+    }
     if (alive) {
       if (row)
         alive = !fwd_step<1, TEX, APP>(st, s, w, r, 0, rec, max_record, cnt, dist_on, row);
