@@ -378,7 +378,19 @@ def main():
                                            gs, gd, gt)
         s = timed(fb, max(2, args.steps // 2), 1)
         extras["fwd_bwd_f32_mrays_s"] = round(rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
-        del gs, gd, gt
+        # the same with binary16 texels (colour from f16, gradients in FP32)
+        dsh = ds.with_arrays(texels=voro.voro_cast_texels(ds.texels, "float16"))
+
+        def fb16():
+            voro.voro_prepare(dsh)
+            for i in range(N_POSES):
+                frame(i, params, dsh)
+                voro.voro_render_views_bwd(dsh, [ccams[i]], rgb, T, None, g_rgb, None, params_bwd,
+                                           gs, gd, gt)
+        s = timed(fb16, max(2, args.steps // 2), 1)
+        extras["fwd_bwd_float16_mrays_s"] = round(
+            rays_per_step * max(2, args.steps // 2) / s / 1e6, 2)
+        del gs, gd, gt, dsh
         # cell-skip sweep (Sec. 5.6 / the supplementary threshold table): the
         # colour of a segment with weight below skip_w is not looked up
         sweep = []
