@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   __shared__ float s_vals[16 * kTableCap];
   __shared__ int s_unit;
   __shared__ int s_okeys[4][kOutbox];
-  __shared__ float s_ovals[4][16 * kOutbox];
+  __shared__ float s_ovals[4][kStageStride * kOutbox];
   GradTable tab;
   tab.keys = s_keys;
   tab.vals = s_vals;

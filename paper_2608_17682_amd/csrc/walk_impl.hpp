@@ -392,11 +392,14 @@ __device__ __forceinline__ float* record_addr(const Grads& g, int key, int c, in
 
 // Per-wave LDS staging of records bound for global memory: 16 lanes then
 // write one record's 16 terms with one instruction, so a record costs about
-// four cache-line requests at the L2 atomic units instead of sixteen.
+// four cache-line requests at the L2 atomic units instead of sixteen.  The
+// same area stages records bound for the workgroup table (see
+// emit_records), laid out [record][kStageStride].
 constexpr int kOutbox = 64;
+constexpr int kStageStride = 17;  // odd: both access patterns spread over the banks
 struct Outbox {
   int* keys;    // [kOutbox]
-  float* vals;  // [16][kOutbox]
+  float* vals;  // [kStageStride * kOutbox]
 };
 
 // Every lane of the wave must call this; `send` lanes hand over (key, v).
@@ -464,6 +467,19 @@ __device__ __forceinline__ bool table_add(const GradTable& t, int key, const flo
     }
   }
   return false;
+}
+
+// the record's table slot (claimed if new), or -1 when kTableProbes probes
+// find neither the key nor an empty slot
+__device__ __forceinline__ int table_slot(const GradTable& t, int key) {
+  const unsigned h = ((unsigned)key * 2654435761u) >> (32 - kTableBits);
+  for (int p = 0; p < kTableProbes; ++p) {
+    const int slot = (int)((h + (unsigned)p) & (kTableCap - 1));
+    int k = __hip_atomic_load(&t.keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == -1) k = atomicCAS(&t.keys[slot], -1, key);
+    if (k == -1 || k == key) return slot;
+  }
+  return -1;
 }
 
 // all threads of the workgroup, after a barrier: every entry to global
@@ -534,7 +550,13 @@ __device__ __forceinline__ void merge_level(int& key, float (&v)[16], int lane) 
 // 0: no record).
 // The texel term of tap t and channel ch is tap weight t x m_ch.  C0 = 4
 // marks a texel-only record (ds and dp are zero and skipped).
-template <int LPR, int C0 = 0>
+// SPREAD: each survivor only claims its table slot and stages its terms;
+// then 16 lanes per record add them, so one LDS add instruction covers four
+// records instead of one term of every survivor.  It needs a few more
+// registers: a win for the full appearance model, whose two records per step
+// already hold it at two waves per SIMD (3.58 -> 3.02 ms per frame), a loss
+// for the single map, which it would push from three waves to two.
+template <int LPR, int C0 = 0, bool SPREAD = false>
 __device__ __forceinline__ void emit_records(int key, float ds, float px, float py, float pz,
                                              const Taps& tp, float mr, float mg, float mb, int lane,
                                              int RR, int R, const Grads& g, const GradTable* tab,
@@ -557,8 +579,34 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
   if constexpr (LPR <= 8) merge_level<8, C0>(key, v, lane);
   if constexpr (LPR <= 16) merge_level<16, C0>(key, v, lane);
   merge_level<32, C0>(key, v, lane);
-  const bool over = key >= 0 && !(tab && table_add<C0>(*tab, key, v));
-  outbox_send(ob, over, key, v, lane, g, RR, R);
+  if constexpr (SPREAD) {
+    int slot = -1;
+    if (key >= 0 && tab) slot = table_slot(*tab, key);
+    const unsigned long long m = __ballot(slot >= 0);
+    if (m) {
+      const int pos = __popcll(m & ((1ull << lane) - 1ull));
+      if (slot >= 0) {
+        ob.keys[pos] = slot;
+#pragma unroll
+        for (int c = C0; c < 16; ++c) ob.vals[pos * kStageStride + c] = v[c];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const int n = __popcll(m);
+      for (int b = 0; b < n; b += 4) {
+        const int r = b + (lane >> 4);
+        const int c = lane & 15;
+        if (r < n && c >= C0) {
+          const float x = ob.vals[r * kStageStride + c];
+          if (x != 0.0f) atomicAdd(&tab->vals[c * kTableCap + ob.keys[r]], x);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    outbox_send(ob, key >= 0 && slot < 0, key, v, lane, g, RR, R);
+  } else {
+    const bool over = key >= 0 && !(tab && table_add<C0>(*tab, key, v));
+    outbox_send(ob, over, key, v, lane, g, RR, R);
+  }
 }
 
 // Every lane of the wave must call this; has_ray = false for lanes without a
@@ -815,17 +863,18 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         cur = ex.next;
       }
     }
-    emit_records<LPR>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane, RR, R, g, tab,
-                      ob);
+    emit_records<LPR, 0, APP == 1>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane,
+                                   RR, R, g, tab, ob);
     if constexpr (APP == 1)
-      emit_records<LPR, 4>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R, g,
-                           tab, ob);
+      emit_records<LPR, 4, true>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R,
+                                 g, tab, ob);
   }
   // the last visited cell, and the unvisited cell behind an early-stopped ray's exit face
-  emit_records<LPR>(lead && a_cell >= 0 ? (a_cell * MAPS) * RR + a_tp.base : -1, a_ds, a_px, a_py,
-                    a_pz, a_tp, a_mr, a_mg, a_mb, lane, RR, R, g, tab, ob);
-  emit_records<LPR>(lead && c_cell >= 0 ? (c_cell * MAPS) * RR + tp.base : -1, 0.0f, c_px, c_py,
-                    c_pz, tp, 0.0f, 0.0f, 0.0f, lane, RR, R, g, tab, ob);
+  emit_records<LPR, 0, APP == 1>(lead && a_cell >= 0 ? (a_cell * MAPS) * RR + a_tp.base : -1,
+                                 a_ds, a_px, a_py, a_pz, a_tp, a_mr, a_mg, a_mb, lane, RR, R, g,
+                                 tab, ob);
+  emit_records<LPR, 0, APP == 1>(lead && c_cell >= 0 ? (c_cell * MAPS) * RR + tp.base : -1, 0.0f,
+                                 c_px, c_py, c_pz, tp, 0.0f, 0.0f, 0.0f, lane, RR, R, g, tab, ob);
 }
 
 }  // namespace voro
