@@ -342,18 +342,24 @@ def main():
     algo_bytes_frame = step_bytes(stats, 16, rays_per_step) / N_POSES
     achieved = algo_bytes_frame / (frame_ms * 1e-3) / 1e9
     traffic = None
+    unit_busy = None
     tfile = os.path.join(ROOT, "profiles", "traffic_views_fwd_shell100k_800x800.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             tj = json.load(f)
         if tj.get("source_hash") == source_hash():
             traffic = tj.get("bytes_per_launch")
+            unit_busy = tj.get("unit_busy")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_views_fwd", "launch_ms": round(frame_ms, 4),
                 "algorithmic_bytes_per_launch": int(algo_bytes_frame),
                 "mean_cells_per_ray": round(stats["steps"] / max(1, stats["rays"]), 2),
                 "mean_degree": round(stats["degree_sum"] / max(1, stats["steps"]), 2)}
+    if unit_busy:
+        # the cache-resident walk beats the HBM roofline; what bounds it is
+        # the issue rate and the texture path, from the committed counters
+        roofline["unit_busy"] = {k: v for k, v in unit_busy.items() if k != "note"}
 
     extras = {"cells_per_ray": k_dist, "fp64_redecisions_per_step": stats["fp64_redecide"]}
     if not args.no_extras:
