@@ -114,7 +114,7 @@ typedef struct voro_scene {
   int32_t tex_res;   /* R in [VORO_MIN_TEX_RES, VORO_MAX_TEX_RES] */
   int32_t tex_dtype; /* VORO_TEX_* */
   int32_t tex_maps;  /* per-cell appearance: 0/1 = one map, 2 = surface + view, 3 = SH */
-  int64_t n_edges;   /* M = nbr_off[N]; M + 3 N < 2^31 */
+  int64_t n_edges;   /* M = nbr_off[N] < 2^31 */
   const float* sites;
   const float* density;
   const int32_t* nbr_off;
@@ -230,10 +230,11 @@ voro_status voro_default_params(voro_params* p);
 /*
  * Bytes of device workspace the scene needs: packed cell records
  * (32 B per cell: position, density, adjacency row), packed edge records
- * (16 B per adjacency entry: (p_j - p_i)/|p_j - p_i|^2 and j, each row padded
- * to a multiple of 4 entries, so at most M + 3 N records), the nearest-site search's
- * partial results and the persistent launch's work counters.  Host-only;
- * needs no device.
+ * (16 B per adjacency entry: (p_j - p_i)/|p_j - p_i|^2 and j, stored at the
+ * adjacency's own offsets with no padding, so M records), their binary16
+ * copies (8 B per entry, for the edge_fp16 variant), the nearest-site
+ * search's partial results and the persistent launch's work counters.
+ * Host-only; needs no device.
  */
 voro_status voro_workspace_size(const voro_scene* scene, size_t* bytes);
 

@@ -1,27 +1,23 @@
-"""Batch evaluation of the oracle in its own process (test infrastructure).
+"""Many-ray evaluation of the oracle over a process pool (test infrastructure).
 
-    python -m oracle.batch SCENE.npz RAYS.npz OUT.npz [WORKERS]
+``evaluate`` renders rays one by one with ``render.render_ray`` in forked
+worker processes and returns, per ray, what the parity tests compare: colour,
+transmittance, the number of visited cells, the visited-cell sequence and the
+degeneracy flags of ``margins``; ``sparse_gradients`` sums the FP64 adjoint
+(``adjoint.grad_ray``) of chosen rays into per-cell gradients of the cells
+they touch.  Nothing here adds arithmetic of its own: the results are those
+of ``render_rays`` / ``grad_rays``, in the same order, computed in parallel.
 
-SCENE.npz holds sites, density, texels (float32 arrays; the adjacency is not
-read).  RAYS.npz holds o [R,3], d [R,3], tmax [R] (float32) and optionally
-g_rgb [R,3], g_T [R] (upstream gradients), start [R], t_stop, skip_w,
-texel_dtype = "float16" (texels rounded to binary16 before use) and
-grad_skip_degenerate (sum gradients over the non-degenerate rays only).  Writes rgb [R,3],
-T [R], K [R], cells [R,128] (-1 padded), degenerate [R] and stop_degenerate [R]
-(oracle.margins), and
-with upstream gradients the FP64 gradients restricted to the touched cells:
-grad_cells [C], grad_sites [C,3], grad_density [C], grad_texels [C,R,R,4].
-
-Running as a separate process lets a caller that already holds the GPU use
-forked workers here without forking itself.
+Workers are forked, so a caller that already holds a GPU must not call this
+(run it from a process that has not initialised one).
 """
 from __future__ import annotations
 
-import sys
+import os
 
 import numpy as np
 
-from . import adjoint, margins, render
+from . import adjoint, margins, render, walk
 
 _G = None
 
@@ -32,24 +28,58 @@ def _init(sites, density, texels, kw):
 
 
 def _job(args):
-    o, d, tm, st, gr, gt, skip_degenerate = args
+    lo, o, d, tm, st, keep = args
     sites, density, texels, kw = _G
+    t_stop = kw.get("t_stop", 1e-4)
     out = []
     for r in range(len(o)):
+        if tm[r] <= 0.0:
+            out.append((np.zeros(3), 1.0, 0, np.zeros(0, np.int64), False, False, None))
+            continue
         rec = render.render_ray(sites, density, texels, o[r], d[r], float(tm[r]),
                                 start=None if st is None else int(st[r]), **kw)
-        deg = margins.degenerate(rec, kw.get("t_stop", 1e-4), float(tm[r]))
-        sdeg = margins.stop_degenerate(rec, kw.get("t_stop", 1e-4))
-        grad = None
-        if gr is not None and not (skip_degenerate and deg):
-            g_sites = _Sparse3()
-            g_den = _Sparse1()
-            g_tex = _SparseTex(texels.shape[1])
-            adjoint.grad_ray(sites, density, texels, o[r], d[r], float(tm[r]), rec, gr[r], gt[r],
-                             g_sites, g_den, g_tex)
-            grad = (g_sites.d, g_den.d, g_tex.d)
-        out.append((rec.rgb, rec.T, rec.K, rec.cells[:128], deg, grad, sdeg))
-    return out
+        deg = margins.degenerate(rec, t_stop, float(tm[r]))
+        sdeg = margins.stop_degenerate(rec, t_stop)
+        out.append((rec.rgb, rec.T, rec.K, np.asarray(rec.cells, np.int64), deg, sdeg,
+                    rec if keep[r] else None))
+    return lo, out
+
+
+def evaluate(sites, density, texels, o, d, tmax, starts=None, keep_records=None,
+             workers=None, chunk=None, **kw):
+    """Oracle results of R rays (FP64), in ray order.
+
+    Returns a dict: rgb [R,3], T [R], K [R], cells (list of R int64 arrays),
+    degenerate [R], stop_degenerate [R] and records (list: the RayRecord of
+    each ray with keep_records[r] set, else None).  Rays with tmax <= 0 are
+    empty (rgb 0, T 1, K 0).  ``kw`` goes to ``render.render_ray``.
+    """
+    import multiprocessing as mp
+    sites = walk.as64(sites)
+    density = walk.as64(density)
+    R = len(o)
+    tm = np.broadcast_to(np.asarray(tmax, np.float64), (R,))
+    keep = np.zeros(R, bool) if keep_records is None else np.asarray(keep_records, bool)
+    workers = workers or min(16, os.cpu_count() or 1)
+    chunk = chunk or max(1, R // (4 * workers))
+    jobs = [(s, o[s:s + chunk], d[s:s + chunk], tm[s:s + chunk],
+             None if starts is None else starts[s:s + chunk], keep[s:s + chunk])
+            for s in range(0, R, chunk)]
+    if workers <= 1:
+        _init(sites, density, texels, kw)
+        parts = [_job(j) for j in jobs]
+    else:
+        ctx = mp.get_context("fork")
+        with ctx.Pool(workers, initializer=_init, initargs=(sites, density, texels, kw)) as pool:
+            parts = pool.map(_job, jobs, chunksize=1)
+    res = [x for _, part in sorted(parts, key=lambda p: p[0]) for x in part]
+    return {"rgb": np.array([x[0] for x in res]).reshape(R, 3),
+            "T": np.array([x[1] for x in res], np.float64),
+            "K": np.array([x[2] for x in res], np.int64),
+            "cells": [x[3] for x in res],
+            "degenerate": np.array([x[4] for x in res], bool),
+            "stop_degenerate": np.array([x[5] for x in res], bool),
+            "records": [x[6] for x in res]}
 
 
 class _Sparse3:
@@ -81,75 +111,38 @@ class _SparseTex:
         self.res = res
         self.d = {}
 
+    def _cell(self, i):
+        return self.d.setdefault(int(i), np.zeros((self.res, self.res, 4)))
+
     def __getitem__(self, key):
-        i = int(key[0])
-        cell = self.d.setdefault(i, np.zeros((self.res, self.res, 4)))
-        return cell[key[1:]]
+        return self._cell(key[0])[key[1:]]
 
     def __setitem__(self, key, v):
-        i = int(key[0])
-        cell = self.d.setdefault(i, np.zeros((self.res, self.res, 4)))
-        cell[key[1:]] = v
+        self._cell(key[0])[key[1:]] = v
 
 
-def main(argv):
-    import multiprocessing as mp
-    import os
-    scene_path, rays_path, out_path = argv[:3]
-    workers = int(argv[3]) if len(argv) > 3 else min(16, os.cpu_count() or 1)
-    z = np.load(scene_path, allow_pickle=False)
-    sites, density, texels = z["sites"], z["density"], z["texels"]
-    rz = np.load(rays_path, allow_pickle=False)
-    if "texel_dtype" in rz and str(rz["texel_dtype"]) == "float16":
-        # the GPU stores binary16 texels: evaluate on their exact values
-        texels = texels.astype(np.float16).astype(np.float32)
-    o, d, tm = rz["o"], rz["d"], rz["tmax"]
-    st = rz["start"] if "start" in rz else None
-    gr = rz["g_rgb"] if "g_rgb" in rz else None
-    gt = rz["g_T"] if "g_T" in rz else (None if gr is None else np.zeros(len(o)))
-    skip_deg = bool(rz["grad_skip_degenerate"]) if "grad_skip_degenerate" in rz else False
-    kw = {}
-    for k in ("t_stop", "skip_w"):
-        if k in rz:
-            kw[k] = float(rz[k])
-    R = len(o)
-    chunk = max(1, R // (4 * workers))
-    jobs = []
-    for s in range(0, R, chunk):
-        e = min(R, s + chunk)
-        jobs.append((o[s:e], d[s:e], tm[s:e], None if st is None else st[s:e],
-                     None if gr is None else gr[s:e], None if gt is None else gt[s:e], skip_deg))
-    ctx = mp.get_context("fork")
-    with ctx.Pool(workers, initializer=_init, initargs=(sites, density, texels, kw)) as pool:
-        res = [x for part in pool.map(_job, jobs) for x in part]
-    out = {"rgb": np.array([x[0] for x in res]), "T": np.array([x[1] for x in res]),
-           "K": np.array([x[2] for x in res]), "degenerate": np.array([x[4] for x in res]),
-           "stop_degenerate": np.array([x[6] for x in res])}
-    cells = np.full((R, 128), -1, np.int64)
-    for r, x in enumerate(res):
-        cells[r, :len(x[3])] = x[3]
-    out["cells"] = cells
-    if gr is not None:
-        acc_s, acc_d, acc_t = {}, {}, {}
-        for x in res:
-            if x[5] is None:
-                continue
-            gs, gd, gtx = x[5]
-            for i, v in gs.items():
-                acc_s[i] = acc_s.get(i, 0.0) + v
-            for i, v in gd.items():
-                acc_d[i] = acc_d.get(i, 0.0) + v
-            for i, v in gtx.items():
-                acc_t[i] = acc_t.get(i, 0.0) + v
-        ids = np.array(sorted(set(acc_s) | set(acc_d) | set(acc_t)), np.int64)
-        res_ = texels.shape[1]
-        out["grad_cells"] = ids
-        out["grad_sites"] = np.array([acc_s.get(int(i), np.zeros(3)) for i in ids]).reshape(-1, 3)
-        out["grad_density"] = np.array([acc_d.get(int(i), 0.0) for i in ids])
-        out["grad_texels"] = np.array([acc_t.get(int(i), np.zeros((res_, res_, 4)))
-                                       for i in ids]).reshape(-1, res_, res_, 4)
-    np.savez(out_path, **out)
+def sparse_gradients(sites, density, texels, o, d, tmax, records, g_rgb, g_T=None):
+    """FP64 gradients of L = sum_r g_rgb[r].rgb[r] + g_T[r] T[r] over the rays
+    whose record is given (records[r] None = ray left out), restricted to the
+    cells they touch.  Single-map appearance (texels [N,R,R,4]).
 
-
-if __name__ == "__main__":
-    main(sys.argv[1:])
+    Returns (cells [C] sorted, g_sites [C,3], g_density [C], g_texels [C,R,R,4]);
+    every cell not listed has zero gradient.
+    """
+    sites = walk.as64(sites)
+    density = walk.as64(density)
+    res = texels.shape[1]
+    gs, gd, gt = _Sparse3(), _Sparse1(), _SparseTex(res)
+    R = len(records)
+    tm = np.broadcast_to(np.asarray(tmax, np.float64), (R,))
+    for r, rec in enumerate(records):
+        if rec is None:
+            continue
+        adjoint.grad_ray(sites, density, texels, o[r], d[r], float(tm[r]), rec, g_rgb[r],
+                         0.0 if g_T is None else g_T[r], gs, gd, gt)
+    ids = np.array(sorted(set(gs.d) | set(gd.d) | set(gt.d)), np.int64)
+    return (ids,
+            np.array([gs.d.get(int(i), np.zeros(3)) for i in ids]).reshape(-1, 3),
+            np.array([gd.d.get(int(i), 0.0) for i in ids]),
+            np.array([gt.d.get(int(i), np.zeros((res, res, 4))) for i in ids]).reshape(
+                -1, res, res, 4))

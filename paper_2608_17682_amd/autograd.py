@@ -84,16 +84,52 @@ class VoroRenderViews(torch.autograd.Function):
         return gs, gd, gt, None, None, None, None, None
 
 
+# walk parameters: they decide the cell sequence and the colour, so the
+# adjoint's replay must use the forward's values
+_WALK_FIELDS = ("t_stop", "skip_w", "max_steps", "tie_window", "appearance", "edge_fp16")
+# launch shape: results do not depend on it, each direction may use its own
+_LAUNCH_FIELDS = ("lanes_per_ray", "tile_w", "tile_h", "block", "schedule")
+
+
+def _wants_grad(*ts) -> bool:
+    return torch.is_grad_enabled() and any(t.requires_grad for t in ts)
+
+
+def _check_differentiable(params):
+    if params.skip_w != 0.0:
+        raise ValueError("skip_w must be 0 when gradients are needed")
+    if params.edge_fp16 != 0:
+        raise ValueError("edge_fp16 is a forward-only inference variant: the adjoint replays "
+                         "the exact walk, so gradients need edge_fp16 = 0")
+
+
+def backward_params(params_fwd, params_bwd=None):
+    """The adjoint's parameters: the forward's walk parameters with params_bwd's
+    launch shape.  Raises ValueError if params_bwd sets a walk parameter
+    (t_stop, skip_w, max_steps, tie_window, appearance, edge_fp16) other than
+    the forward's: the replay would visit other cells."""
+    q = voro.voro_params.from_buffer_copy(params_fwd)
+    if params_bwd is not None:
+        for f in _WALK_FIELDS:
+            if getattr(params_bwd, f) != getattr(params_fwd, f):
+                raise ValueError(f"params_bwd.{f} = {getattr(params_bwd, f)} differs from the "
+                                 f"forward's {getattr(params_fwd, f)}; only the launch shape "
+                                 f"({', '.join(_LAUNCH_FIELDS)}) may differ")
+        for f in _LAUNCH_FIELDS:
+            setattr(q, f, getattr(params_bwd, f))
+    return q
+
+
 def render_views(sites, density, texels, nbr_off, nbr_idx, cams, params_fwd=None,
                  params_bwd=None):
     """Differentiable render of camera views (voro_camera list or objects with
-    the camera attributes); pixels of all views concatenated in order."""
+    the camera attributes); pixels of all views concatenated in order.
+    params_bwd supplies only the adjoint's launch shape (see backward_params)."""
     cams = voro.camera_array(cams)
     params_fwd = params_fwd or voro.default_params()
-    params_bwd = params_bwd or voro.default_params()
-    if params_fwd.skip_w != 0.0 and torch.is_grad_enabled() and (
-            sites.requires_grad or density.requires_grad or texels.requires_grad):
-        raise ValueError("skip_w must be 0 when gradients are needed")
+    params_bwd = backward_params(params_fwd, params_bwd)
+    if _wants_grad(sites, density, texels):
+        _check_differentiable(params_fwd)
     return VoroRenderViews.apply(sites, density, texels, nbr_off, nbr_idx, cams, params_fwd,
                                  params_bwd)
 
@@ -105,8 +141,7 @@ def render(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params=N
     differentiable like the colour."""
     if params is None:
         params = voro.default_params()
-    if params.skip_w != 0.0 and torch.is_grad_enabled() and (
-            sites.requires_grad or density.requires_grad or texels.requires_grad):
-        raise ValueError("skip_w must be 0 when gradients are needed")
+    if _wants_grad(sites, density, texels):
+        _check_differentiable(params)
     return VoroRender.apply(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params,
                             bool(distortion))

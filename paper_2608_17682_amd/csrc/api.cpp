@@ -43,9 +43,8 @@ voro_status check_scene(const voro_scene* s) {
     return fail(VORO_EINVAL, "unknown tex_dtype %d", s->tex_dtype);
   if (s->tex_maps < 0 || s->tex_maps > 3)
     return fail(VORO_EINVAL, "tex_maps must be 0, 1, 2 or 3 (got %d)", s->tex_maps);
-  if (s->n_edges < 0 || s->n_edges + 3 * (int64_t)s->n_sites >= ((int64_t)1 << 31))
-    return fail(VORO_EINVAL, "n_edges %lld out of range (n_edges + 3 n_sites must be < 2^31)",
-                (long long)s->n_edges);
+  if (s->n_edges < 0 || s->n_edges >= ((int64_t)1 << 31))
+    return fail(VORO_EINVAL, "n_edges %lld out of range [0, 2^31)", (long long)s->n_edges);
   if (!s->sites || !s->density || !s->nbr_off || !s->texels)
     return fail(VORO_EINVAL, "scene has a NULL array");
   if (s->n_edges > 0 && !s->nbr_idx) return fail(VORO_EINVAL, "nbr_idx is NULL");

@@ -1,36 +1,38 @@
-"""GPU parity at the full scene sizes - 2M sites (one 1280x840 interior view,
-forward and adjoint) and 4M sites (8 mixed views in one persistent launch,
-binary16 texels) - on sampled rays the oracle evaluates one by one, in the
-launch configuration bench.py times (Morton-ordered cells, default launch
-parameters).  The oracle runs in a child process (oracle.batch)."""
+"""GPU parity at the full scene sizes against the FP64 oracle's stored results.
+
+* 2M sites on 20 ellipsoid surfaces, one 1280x840 interior view, FP32
+  texels: 256 sampled rays (tests/golden/config3_rays.npz).
+* 4M sites in the shell structure, binary16 texels, 8 mixed views in one
+  launch (2 pinhole, 2 equidistant fisheye, 2 rolling shutter, 2 thin lens
+  with 4 samples per pixel): 256 sampled pixels per view, 64 for the thin
+  lens (tests/golden/config5_views.npz).
+
+Both files are written by tests/golden/make_goldens.py from oracle/ alone
+(brute force over all sites, FP64); each records a fingerprint of the scene
+arrays, checked here against the scene these tests build.  Images come from
+the launch configurations bench.py times (Morton-ordered cells, tuned launch
+shapes); sequences from the oracle's own FP32 rays through the explicit-ray
+entry point.  Tolerances: colour and transmittance 1e-4 on every ray but the
+stop-degenerate ones, cell counts and sequences bit-exact on the
+non-degenerate ones, gradients within 1e-4 of the largest component of
+each kind (FP32 atomics in a different order), exact zeros elsewhere.
+"""
 import os
-import subprocess
-import sys
-import tempfile
 
 import numpy as np
 import pytest
 import torch
 
-from oracle import cameras
-from paper_2608_17682_amd import synth, voro
-from helpers import f32
+from paper_2608_17682_amd import autotune, synth, voro
+from paper_2608_17682_amd.autograd import render_views
+from helpers import scene_fingerprint, seq_hash
 
-pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1500)]
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def announce(msg):
     print(f"[gpu-case] {msg}", flush=True)
-
-
-def run_oracle(scene_path, rays):
-    td = tempfile.mkdtemp()
-    rp, op = os.path.join(td, "rays.npz"), os.path.join(td, "out.npz")
-    np.savez(rp, **rays)
-    subprocess.run([sys.executable, "-m", "oracle.batch", scene_path, rp, op], check=True, cwd=ROOT)
-    z = np.load(op, allow_pickle=False)
-    return {k: z[k] for k in z.files}
 
 
 @pytest.fixture(scope="module")
@@ -45,6 +47,11 @@ def to_dev(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
+def load_golden(name):
+    z = np.load(os.path.join(GOLDEN, name), allow_pickle=False)
+    return {k: z[k] for k in z.files}
+
+
 def morton_scene(scene, dev, tex_dtype=None):
     ds0 = voro.device_scene(scene, dev, tex_dtype=tex_dtype)
     ds, perm, inv = voro.voro_morton_reorder(ds0)
@@ -53,11 +60,58 @@ def morton_scene(scene, dev, tex_dtype=None):
     return ds, perm.cpu().numpy(), inv.cpu().numpy()
 
 
-def assert_grad_close(got, want, name):
-    scale = max(1e-12, float(np.abs(want).max()))
-    err = float(np.abs(got - want).max())
-    assert err <= 1e-4 * scale + 1e-6, (name, err, scale)
+def dense_texel_grads(g):
+    """The golden's sparse texel gradients as [C,R,R,3] over its touched cells."""
+    res = int(g["grad_tex_res"])
+    out = np.zeros((len(g["grad_cells"]) * res * res, 3))
+    out[g["grad_tex_index"]] = g["grad_tex_rgb"]
+    return out.reshape(-1, res, res, 3)
 
+
+def assert_grads_match(g, gs, gd, gt, inv, what):
+    """GPU gradients (Morton order, dense) against the oracle's touched cells."""
+    ids = g["grad_cells"]
+    k = inv[ids]
+    want = {"sites": g["grad_sites"], "density": g["grad_density"],
+            "texels": dense_texel_grads(g)}
+    got = {"sites": gs[k], "density": gd[k], "texels": gt[k][..., :3]}
+    for name in want:
+        scale = max(1e-12, float(np.abs(want[name]).max()))
+        err = float(np.abs(got[name] - want[name]).max())
+        announce(f"{what} {name}: max err {err:.2e} of max |grad| {scale:.2e}")
+        assert err <= 1e-4 * scale + 1e-6, (what, name, err, scale)
+    mask = np.ones(len(gd), bool)
+    mask[k] = False
+    assert np.all(gd[mask] == 0) and np.all(gs[mask] == 0) and np.all(gt[mask] == 0), what
+    assert np.all(gt[..., 3] == 0)
+
+
+def check_sequences(ds, perm, inv, g, dev, params, what):
+    """Explicit-ray walk of the oracle's FP32 rays: K and sequences bit-exact
+    on the non-degenerate rays, colours within 1e-4 on the non-stop-degenerate."""
+    R = len(g["o"])
+    kmax = int(g["K"].max()) + 16
+    O, D, TM = to_dev(g["o"], dev), to_dev(g["d"], dev), to_dev(g["tmax"], dev)
+    S = to_dev(inv[g["start"]].astype(np.int32), dev)
+    p = voro.voro_params.from_buffer_copy(params)
+    p.max_record = kmax
+    nsteps = torch.empty(R, dtype=torch.int32, device=dev)
+    cells = torch.empty((R, kmax), dtype=torch.int32, device=dev)
+    rgb, T = voro.voro_render_fwd(ds, O, D, TM, S, p, nsteps=nsteps, cells=cells)
+    K, cells = nsteps.cpu().numpy(), cells.cpu().numpy()
+    ok = ~g["degenerate"]
+    assert ok.mean() > 0.9, ok.mean()
+    assert np.array_equal(K[ok], g["K"][ok])
+    mism = [r for r in np.nonzero(ok)[0] if seq_hash(perm[cells[r, :K[r]]]) != int(g["seq_hash"][r])]
+    assert not mism, f"{what}: {len(mism)} sequences differ, first rays {mism[:5]}"
+    sd = ~g["stop_degenerate"]
+    assert np.abs(rgb.cpu().numpy() - g["rgb"])[sd].max() <= 1e-4
+    assert np.abs(T.cpu().numpy() - g["T"])[sd].max() <= 1e-4
+    announce(f"{what}: {ok.sum()} of {R} sequences equal (mean K {K.mean():.1f}, max {K.max()})")
+    return rgb, T
+
+
+# ------------------------------------------------------------------ 2M sites
 
 class Case:
     pass
@@ -66,147 +120,137 @@ class Case:
 @pytest.fixture(scope="module")
 def c3(dev):
     c = Case()
+    c.g = load_golden("config3_rays.npz")
     announce("config3: 2M-site scene (built by a child process on a cache miss)")
     c.scene = synth.scene_cached("config3")
+    assert scene_fingerprint(c.scene) == str(c.g["fingerprint"])
     c.cam = synth.config3_camera(c.scene)
-    o, d, tm, _ = cameras.camera_rays_of(c.cam)
-    c.pick = synth.sample_pixels(c.cam.n_pixels, 24, 33)
-    c.o, c.d, c.tm = f32(o[c.pick]), f32(d[c.pick]), f32(tm[c.pick])
-    c.g_rgb = synth.upstream(len(c.pick), 3, with_gT=False)[0]
-    announce("config3: oracle on 24 sampled rays")
-    c.orc = run_oracle(synth.scene_cache_path("config3"),
-                       dict(o=c.o, d=c.d, tmax=c.tm, g_rgb=c.g_rgb,
-                            g_T=np.zeros(len(c.pick), np.float32),
-                            grad_skip_degenerate=np.array(True)))
+    assert np.array_equal(c.cam.c2w, c.g["cam_c2w"])
     c.ds, c.perm, c.inv = morton_scene(c.scene, dev)
+    c.pf = autotune.params_for("config3", "fwd")
+    c.pb = autotune.params_for("config3", "bwd")
     return c
 
 
-def test_config3_forward_sampled_rays(dev, c3):
-    announce("config3: forward of the sampled rays")
-    O, D, TM = to_dev(c3.o, dev), to_dev(c3.d, dev), to_dev(c3.tm, dev)
-    S = voro.voro_locate_origins(c3.ds, O[:1]).expand(len(c3.o)).contiguous()
-    R = len(c3.o)
-    p = voro.default_params(max_record=128)
-    nsteps = torch.empty(R, dtype=torch.int32, device=dev)
-    cells = torch.empty((R, 128), dtype=torch.int32, device=dev)
-    rgb, T = voro.voro_render_fwd(c3.ds, O, D, TM, S, p, nsteps=nsteps, cells=cells)
-    rgb, T, K, cells = (x.cpu().numpy() for x in (rgb, T, nsteps, cells))
-    np.testing.assert_allclose(rgb, c3.orc["rgb"], atol=1e-4, rtol=0)
-    np.testing.assert_allclose(T, c3.orc["T"], atol=1e-4, rtol=0)
-    ok = ~c3.orc["degenerate"]
-    assert ok.mean() > 0.8
-    for r in np.nonzero(ok)[0]:
-        k = int(c3.orc["K"][r])
-        assert K[r] == k
-        kk = min(k, 128)
-        np.testing.assert_array_equal(c3.perm[cells[r, :kk]], c3.orc["cells"][r, :kk])
-    assert K.mean() > 20
+def test_config3_sequences_and_colours(dev, c3):
+    announce("config3: explicit oracle rays, 256 sampled")
+    check_sequences(c3.ds, c3.perm, c3.inv, c3.g, dev, c3.pf, "config3")
 
 
 def test_config3_adjoint_sampled_rays(dev, c3):
-    ok = np.nonzero(~c3.orc["degenerate"])[0]
-    announce("config3: adjoint of the sampled rays")
-    O, D, TM = to_dev(c3.o, dev), to_dev(c3.d, dev), to_dev(c3.tm, dev)
-    S = voro.voro_locate_origins(c3.ds, O[:1]).expand(len(c3.o)).contiguous()
-    # the oracle's gradient sums cover the non-degenerate rays
-    sel = ok
-    orc = c3.orc
-    ts = torch.from_numpy(sel).to(dev)
-    rgb, T = voro.voro_render_fwd(c3.ds, O[ts], D[ts], TM[ts], S[ts])
-    gs, gd, gt = voro.voro_render_bwd(c3.ds, O[ts], D[ts], TM[ts], S[ts], rgb, T,
-                                      to_dev(c3.g_rgb[sel], dev))
-    gs, gd, gt = gs.cpu().numpy(), gd.cpu().numpy(), gt.cpu().numpy()
-    ids = orc["grad_cells"]
-    k = c3.inv[ids]                      # Morton index of each oracle cell
-    assert_grad_close(gs[k], orc["grad_sites"], "sites")
-    assert_grad_close(gd[k], orc["grad_density"], "density")
-    assert_grad_close(gt[k], orc["grad_texels"], "texels")
-    mask = np.ones(len(gd), bool)
-    mask[k] = False
-    assert np.all(gd[mask] == 0) and np.all(gs[mask] == 0) and np.all(gt[mask] == 0)
+    announce("config3: adjoint of the non-degenerate sampled rays (explicit rays)")
+    g = c3.g
+    sel = ~g["degenerate"]
+    O, D, TM = (to_dev(g[k][sel], dev) for k in ("o", "d", "tmax"))
+    S = to_dev(c3.inv[g["start"][sel]].astype(np.int32), dev)
+    rgb, T = voro.voro_render_fwd(c3.ds, O, D, TM, S, c3.pf)
+    gs, gd, gt = voro.voro_render_bwd(c3.ds, O, D, TM, S, rgb, T, to_dev(g["g_rgb"][sel], dev),
+                                      None, c3.pb)
+    assert_grads_match(g, gs.cpu().numpy(), gd.cpu().numpy(), gt.cpu().numpy(), c3.inv,
+                       "config3 explicit")
+
+
+def test_config3_benchmark_autograd_step_matches_oracle(dev, c3):
+    announce("config3: the benchmarked autograd render_views step, sampled pixels")
+    g = c3.g
+    ok = ~g["degenerate"]
+    gimg = np.zeros((c3.cam.n_pixels, 3), np.float32)
+    gimg[g["pixels"][ok]] = g["g_rgb"][ok]
+    sites = c3.ds.sites.clone().requires_grad_(True)
+    dens = c3.ds.density.clone().requires_grad_(True)
+    tex = c3.ds.texels.clone().requires_grad_(True)
+    rgb, T = render_views(sites, dens, tex, c3.ds.nbr_off, c3.ds.nbr_idx, [c3.cam], c3.pf, c3.pb)
+    sd = ~g["stop_degenerate"]
+    px = g["pixels"]
+    assert np.abs(rgb.detach().cpu().numpy()[px] - g["rgb"])[sd].max() <= 1e-4
+    assert np.abs(T.detach().cpu().numpy()[px] - g["T"])[sd].max() <= 1e-4
+    (rgb * to_dev(gimg, dev)).sum().backward()
+    assert_grads_match(g, sites.grad.cpu().numpy(), dens.grad.cpu().numpy(),
+                       tex.grad.cpu().numpy(), c3.inv, "config3 render_views")
 
 
 def test_config3_full_frame_views_equals_explicit(dev, c3):
-    announce("config3: full 1280x840 frame, persistent launch vs explicit rays")
-    rgb_v, T_v, _ = voro.voro_render_views_fwd(c3.ds, [c3.cam])
+    announce("config3: full 1280x840 frame, tuned views launch vs explicit rays")
+    rgb_v, T_v, _ = voro.voro_render_views_fwd(c3.ds, [c3.cam], c3.pf)
     O, D, TM = voro.voro_gen_rays([c3.cam], dev)
     S = voro.voro_locate_origins(c3.ds, O[:1]).expand(O.shape[0]).contiguous()
     rgb_e, T_e = voro.voro_render_fwd(c3.ds, O, D, TM, S, voro.default_params(img_w=1280))
     assert torch.equal(rgb_v, rgb_e) and torch.equal(T_v, T_e)
-    # and the sampled pixels against the oracle (FP32 rays from the GPU differ
-    # from the oracle's by rounding only)
-    rgb_v = rgb_v.cpu().numpy()
-    ok = ~c3.orc["stop_degenerate"]
-    np.testing.assert_allclose(rgb_v[c3.pick[ok]], c3.orc["rgb"][ok], atol=1e-4, rtol=0)
 
+
+# ------------------------------------------------------------------ 4M sites
 
 @pytest.fixture(scope="module")
 def c5(dev):
     c = Case()
+    c.g = load_golden("config5_views.npz")
     announce("config5: 4M-site scene (built by a child process on a cache miss)")
     c.scene = synth.scene_cached("config5")
+    assert scene_fingerprint(c.scene) == str(c.g["fingerprint"])
     c.cams = synth.config5_cameras(1.0)
-    rays = {"o": [], "d": [], "tmax": []}
-    c.samples = []  # (view, pixel, first oracle ray, spp)
-    n = 0
-    for v, cam in enumerate(c.cams):
-        o, d, tm, valid = cameras.camera_rays_of(cam)
-        cand = np.nonzero(valid.reshape(cam.n_pixels, cam.spp).all(1))[0]
-        pix = cand[synth.sample_pixels(len(cand), 2, 50 + v)]
-        for p in pix:
-            rs = slice(p * cam.spp, (p + 1) * cam.spp)
-            rays["o"].append(o[rs])
-            rays["d"].append(d[rs])
-            rays["tmax"].append(tm[rs])
-            c.samples.append((v, int(p), n, cam.spp))
-            n += cam.spp
-    rays = {k: f32(np.concatenate(v)) for k, v in rays.items()}
-    rays["texel_dtype"] = np.array("float16")
-    announce(f"config5: oracle on {n} sampled rays (binary16 texels)")
-    c.orc = run_oracle(synth.scene_cache_path("config5"), rays)
     c.ds, c.perm, c.inv = morton_scene(c.scene, dev, tex_dtype="float16")
+    c.pf = autotune.params_for("config5", "fwd")
+    c.pb = autotune.params_for("config5", "bwd")
+    c.off = np.cumsum([0] + [cam.n_pixels for cam in c.cams])
     return c
 
 
-def test_config5_persistent_views_forward(dev, c5):
-    announce("config5: 8 views, one persistent forward launch")
-    p = voro.default_params()
-    rgb, T, ray_rgbT = voro.voro_render_views_fwd(c5.ds, c5.cams, p)
+def test_config5_sequences_and_colours(dev, c5):
+    announce("config5: explicit oracle rays, 256 per view")
+    check_sequences(c5.ds, c5.perm, c5.inv, c5.g, dev, c5.pf, "config5")
+
+
+def test_config5_benchmark_launch_forward(dev, c5):
+    announce("config5: 8 views, the benchmarked forward launch")
+    g = c5.g
+    rgb, T, _ = voro.voro_render_views_fwd(c5.ds, c5.cams, c5.pf)
     rgb, T = rgb.cpu().numpy(), T.cpu().numpy()
-    off = np.cumsum([0] + [cam.n_pixels for cam in c5.cams])
-    checked = 0
-    for v, pix, r0, spp in c5.samples:
-        # colours match on every ray but those whose T lands next to t_stop
-        if c5.orc["stop_degenerate"][r0:r0 + spp].any():
+    checked = np.zeros(8, int)
+    for v, p, r0, spp in zip(g["px_view"], g["px_pixel"], g["px_ray0"], g["px_spp"]):
+        if g["stop_degenerate"][r0:r0 + spp].any():
             continue
-        np.testing.assert_allclose(rgb[off[v] + pix], c5.orc["rgb"][r0:r0 + spp].mean(0),
-                                   atol=1e-4, rtol=0)
-        np.testing.assert_allclose(T[off[v] + pix], c5.orc["T"][r0:r0 + spp].mean(), atol=1e-4,
-                                   rtol=0)
-        checked += 1
-    assert checked >= 14
+        q = c5.off[v] + p
+        assert np.abs(rgb[q] - g["rgb"][r0:r0 + spp].mean(0)).max() <= 1e-4, (v, p)
+        assert abs(T[q] - g["T"][r0:r0 + spp].mean()) <= 1e-4, (v, p)
+        checked[v] += 1
+    announce(f"config5: pixels checked per view {checked.tolist()}")
+    assert np.all(checked >= 0.9 * np.array([256, 256, 256, 256, 256, 256, 64, 64]))
     # fisheye pixels outside the image circle are empty
-    fe = 2
-    W = c5.cams[fe].width
-    assert T[off[fe]] == 1.0 and np.all(rgb[off[fe]] == 0)
+    assert T[c5.off[2]] == 1.0 and np.all(rgb[c5.off[2]] == 0)
+
+
+def test_config5_benchmark_launch_adjoint(dev, c5):
+    announce("config5: the benchmarked adjoint launch, upstream on the gradient pixels only")
+    g = c5.g
+    npx = int(c5.off[-1])
+    g_all = synth.upstream(npx, 5, with_gT=False)[0]
+    gimg = np.zeros((npx, 3), np.float32)
+    for v, p, use in zip(g["px_view"], g["px_pixel"], g["px_grad"]):
+        if use:
+            gimg[c5.off[v] + p] = g_all[c5.off[v] + p]
+    assert g["px_grad"].sum() >= 0.9 * (6 * 32 + 2 * 8)
+    rgb, T, ray = voro.voro_render_views_fwd(c5.ds, c5.cams, c5.pf)
+    gs, gd, gt = voro.voro_render_views_bwd(c5.ds, c5.cams, rgb, T, ray, to_dev(gimg, dev), None,
+                                            c5.pb)
+    assert_grads_match(g, gs.cpu().numpy(), gd.cpu().numpy(), gt.cpu().numpy(), c5.inv,
+                       "config5 views")
 
 
 def test_config5_persistent_views_adjoint_equals_explicit(dev, c5):
-    announce("config5: persistent adjoint vs explicit-ray adjoint, all 7.7M rays")
-    p = voro.default_params()
-    npx = sum(cam.n_pixels for cam in c5.cams)
+    announce("config5: views adjoint vs explicit-ray adjoint, all 7.3M rays")
+    p = c5.pb
+    npx = int(c5.off[-1])
     g_rgb = synth.upstream(npx, 5, with_gT=False)[0]
-    rgb, T, ray_rgbT = voro.voro_render_views_fwd(c5.ds, c5.cams, p)
+    rgb, T, ray_rgbT = voro.voro_render_views_fwd(c5.ds, c5.cams, c5.pf)
     gv = voro.voro_render_views_bwd(c5.ds, c5.cams, rgb, T, ray_rgbT, to_dev(g_rgb, dev), None, p)
     O, D, TM = voro.voro_gen_rays(c5.cams, dev)
-    centres = to_dev(f32([cam.c2w[:, 3] for cam in c5.cams]), dev)
+    centres = to_dev(np.array([cam.c2w[:, 3] for cam in c5.cams], np.float32), dev)
     cc = voro.voro_locate_origins(c5.ds, centres)
     nr = [cam.n_rays for cam in c5.cams]
     hint = torch.cat([cc[i:i + 1].expand(k) for i, k in enumerate(nr)]).contiguous()
     S = voro.voro_locate_origins(c5.ds, O, hint=hint)
-    rgb_e, T_e = voro.voro_render_fwd(c5.ds, O, D, TM, S, p)
-    # the persistent launch's per-ray results are the explicit path's, bit for bit
+    rgb_e, T_e = voro.voro_render_fwd(c5.ds, O, D, TM, S, voro.default_params())
+    # the multi-view launch's per-ray results are the explicit path's, bit for bit
     assert torch.equal(rgb_e, ray_rgbT[:, :3].contiguous()) and torch.equal(T_e, ray_rgbT[:, 3])
     gr = []
     off = 0
@@ -214,7 +258,7 @@ def test_config5_persistent_views_adjoint_equals_explicit(dev, c5):
         gr.append(np.repeat(g_rgb[off:off + cam.n_pixels], cam.spp, 0) / cam.spp)
         off += cam.n_pixels
     ge = voro.voro_render_bwd(c5.ds, O, D, TM, S, rgb_e, T_e, to_dev(np.concatenate(gr), dev),
-                              None, p)
+                              None, voro.default_params())
     for a, b, name in zip(gv, ge, ("sites", "density", "texels")):
         a, b = a.cpu().numpy(), b.cpu().numpy()
         assert np.isfinite(a).all()

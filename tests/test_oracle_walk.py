@@ -121,3 +121,53 @@ def test_csr_symmetric_no_self_loops():
     assert not np.any(rows == idx)
     fwd = set(zip(rows.tolist(), idx.tolist()))
     assert all((j, i) in fwd for i, j in fwd)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "shell", "lattice"])
+def test_per_ray_bisectors_equal_exit_crossing(kind):
+    # The per-ray form (dot products s = p.w, h = |p|^2/2 - p.o taken once)
+    # must take every decision exit_crossing takes: the same next cell, the
+    # same crossing to rounding, the same gap; on the integer lattice exact
+    # ties must still go to the smaller index.
+    rng = np.random.default_rng({"uniform": 0, "shell": 1, "lattice": 2}[kind])
+    if kind == "uniform":
+        sites = rng.uniform(-1, 1, (400, 3)).astype(np.float32)
+    elif kind == "shell":
+        v = rng.normal(size=(400, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        sites = (v + rng.normal(scale=0.01, size=v.shape)).astype(np.float32)
+    else:
+        sites = synth.lattice_sites(6, 1.0)
+    checked = ties = 0
+    for _ in range(8):
+        if kind == "lattice":
+            # axis-aligned rays through lattice planes: many exact ties
+            o = np.round(rng.uniform(-3, 3, 3) * 2) / 2
+            w = np.zeros(3)
+            w[rng.integers(3)] = rng.choice([-1.0, 1.0])
+        else:
+            o = rng.uniform(-1.5, 1.5, 3)
+            w = rng.normal(size=3)
+            w /= np.linalg.norm(w)
+        ray = walk.RayBisectors(sites, o, w)
+        for i in range(0, len(sites), 7):
+            t0, j0, g0 = walk.exit_crossing(sites, i, o, w)
+            t1, j1, g1 = ray.exit(i)
+            assert j1 == j0, (i, t0, t1)
+            if j0 < 0:
+                assert math.isinf(t1) and math.isinf(g1)
+                continue
+            # both forms round n.w differently by ~1e-16: at a grazing face
+            # (small n.w) the crossing moves by |t| 1e-16 / |n.w|
+            b = float((sites[j0].astype(np.float64) - sites[i]) @ w)
+            tol = 1e-12 * max(1.0, abs(t0)) + 4e-16 * abs(t0) / abs(b)
+            assert abs(t1 - t0) <= tol
+            if math.isinf(g0):
+                assert math.isinf(g1)
+            else:
+                assert abs(g1 - g0) <= 2 * tol + 1e-12 * abs(g0)
+                ties += g0 == 0.0
+            checked += 1
+    assert checked > 100
+    if kind == "lattice":
+        assert ties > 10
