@@ -3,33 +3,34 @@
 // storage.  Both run once per scene, outside a frame's timed work.
 #include <hip/hip_runtime.h>
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "host_common.hpp"
 
 namespace voro {
 
 struct ReorderScratch {
-  size_t codes_in, codes_out, vals_in, deg, bbox, cub, total;
-  size_t cub_bytes;
+  size_t codes_in, codes_out, vals_in, deg, bbox, prim, total;
+  size_t prim_bytes;  // rocPRIM's temporary storage (sort and scan share it)
 };
 
 static ReorderScratch reorder_layout(int n, int64_t m) {
   (void)m;
   ReorderScratch L;
   size_t sort_bytes = 0, scan_bytes = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const unsigned*)nullptr,
-                                     (unsigned*)nullptr, (const int*)nullptr, (int*)nullptr, n, 0,
-                                     30);
-  hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, (const int*)nullptr, (int*)nullptr, n);
-  L.cub_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
+  (void)rocprim::radix_sort_pairs(nullptr, sort_bytes, (const unsigned*)nullptr, (unsigned*)nullptr,
+                                  (const int*)nullptr, (int*)nullptr, (size_t)n, 0u, 30u);
+  (void)rocprim::inclusive_scan(nullptr, scan_bytes, (const int*)nullptr, (int*)nullptr, (size_t)n,
+                                rocprim::plus<int>());
+  L.prim_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
   L.codes_in = 0;
   L.codes_out = align256(L.codes_in + (size_t)n * 4);
   L.vals_in = align256(L.codes_out + (size_t)n * 4);
   L.deg = align256(L.vals_in + (size_t)n * 4);
   L.bbox = align256(L.deg + (size_t)n * 4);
-  L.cub = align256(L.bbox + 256 * 8 * 4);
-  L.total = align256(L.cub + L.cub_bytes);
+  L.prim = align256(L.bbox + 256 * 8 * 4);
+  L.total = align256(L.prim + L.prim_bytes);
   return L;
 }
 
@@ -219,21 +220,23 @@ voro_status voro_morton_reorder(const voro_scene* in, const voro_scene* out, int
   int* vals_in = (int*)(base + L.vals_in);
   int* deg = (int*)(base + L.deg);
   float* bbox = (float*)(base + L.bbox);
-  void* cub = base + L.cub;
+  void* prim = base + L.prim;
   const int blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_bbox_partial, dim3(kBBoxBlocks), dim3(256), 0, s, in->sites, n, bbox);
   hipLaunchKernelGGL(k_morton, dim3(blocks), dim3(256), 0, s, in->sites, n, bbox, codes_in, vals_in);
   if ((st = check_launch("voro_morton_reorder: codes")) != VORO_OK) return st;
-  size_t cb = L.cub_bytes;
-  if (hipcub::DeviceRadixSort::SortPairs(cub, cb, codes_in, codes_out, vals_in, perm, n, 0, 30, s) !=
-      hipSuccess)
+  // stable LSD radix sort on the 30 code bits: equal codes keep their order
+  size_t pb = L.prim_bytes;
+  if (rocprim::radix_sort_pairs(prim, pb, codes_in, codes_out, vals_in, perm, (size_t)n, 0u, 30u,
+                                s) != hipSuccess)
     return fail(VORO_EHIP, "voro_morton_reorder: radix sort failed");
   hipLaunchKernelGGL(k_permute_cells, dim3(blocks), dim3(256), 0, s, perm, n, in->sites,
                      in->density, in->nbr_off, const_cast<float*>(out->sites),
                      const_cast<float*>(out->density), inv_perm, deg);
   int* off_out = const_cast<int*>(out->nbr_off);
-  cb = L.cub_bytes;
-  if (hipcub::DeviceScan::InclusiveSum(cub, cb, deg, off_out + 1, n, s) != hipSuccess)
+  pb = L.prim_bytes;
+  if (rocprim::inclusive_scan(prim, pb, deg, off_out + 1, (size_t)n, rocprim::plus<int>(), s) !=
+      hipSuccess)
     return fail(VORO_EHIP, "voro_morton_reorder: scan failed");
   hipLaunchKernelGGL(k_set_first_zero, dim3(1), dim3(1), 0, s, off_out);
   hipLaunchKernelGGL(k_permute_rows, dim3((int)(((long)n * 16 + 255) / 256)), dim3(256), 0, s, perm,

@@ -180,3 +180,33 @@ def test_malformed_adjacency_is_neutralised(dev):
     torch.cuda.synchronize()
     assert torch.isfinite(rgb).all() and torch.isfinite(T).all()
     assert float(T.min()) >= 0.0 and float(T.max()) <= 1.0
+
+
+def test_morton_sort_is_stable_on_equal_codes(dev):
+    # 10x10x10 grid positions, each taken by three cells (equal Morton codes);
+    # distinct positions are far apart in the 1024^3 code grid.  The reorder
+    # must keep each trio together and in its original order.
+    announce("morton reorder: equal codes keep their order")
+    g = (np.arange(10) + 0.5) / 10.0
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(3)
+    order = rng.permutation(3 * len(pos))
+    sites = np.repeat(pos, 3, axis=0)[order].astype(np.float32)
+    n = len(sites)
+    tex = np.zeros((n, 2, 2, 4), np.float32)
+    tex[:, :, :, 0] = np.arange(n, dtype=np.float32)[:, None, None]
+    off = np.zeros(n + 1, np.int32)
+    ds = voro.DeviceScene(to_dev(sites, dev), to_dev(np.ones(n, np.float32), dev),
+                          to_dev(off, dev), torch.zeros(0, dtype=torch.int32, device=dev),
+                          to_dev(tex, dev))
+    ds2, perm, inv = voro.voro_morton_reorder(ds)
+    perm = perm.cpu().numpy()
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    assert np.array_equal(inv.cpu().numpy()[perm], np.arange(n))
+    s2 = ds2.sites.cpu().numpy()
+    np.testing.assert_array_equal(s2, sites[perm])
+    np.testing.assert_array_equal(ds2.texels.cpu().numpy()[:, 0, 0, 0], perm.astype(np.float32))
+    for k in range(0, n, 3):
+        trio = perm[k:k + 3]
+        assert np.all(sites[trio] == sites[trio[0]]), k
+        assert trio[0] < trio[1] < trio[2], (k, trio)

@@ -538,3 +538,6 @@ def test_morton_reorder_preserves_the_image(dev, c1):
         return r
     code = (spread(q[:, 0]) << 2) | (spread(q[:, 1]) << 1) | spread(q[:, 2])
     assert np.all(np.diff(code) >= 0)
+    # the sort is stable: cells with equal codes keep their original order
+    same = np.diff(code) == 0
+    assert np.all(np.diff(perm_n)[same] > 0)
