@@ -261,7 +261,7 @@ def bench_config5(scene, dev, args, timed):
     voro.voro_prepare(ds)
     ccams = [voro.camera_of(c) for c in cams]
     nr, npx = voro.voro_camera_counts(ccams)
-    pf, pb = autotune.params_for("config5", "fwd"), autotune.params_for("config5", "bwd")
+    pf, pb = autotune.params_for(ds, cams, "fwd"), autotune.params_for(ds, cams, "bwd")
     rgb = torch.empty((npx, 3), device=dev)
     T = torch.empty(npx, device=dev)
     ray = torch.empty((nr, 4), device=dev)
@@ -301,8 +301,8 @@ def bench_config5(scene, dev, args, timed):
            "cells_per_ray": {"mean": round(stats["steps"] / max(1, rays), 2),
                              "p50": float(kq[0]), "p99": float(kq[1]),
                              "max": int(ks.max())},
-           "launch_fwd": dict(autotune.lookup("config5", "fwd") or {}),
-           "launch_bwd": dict(autotune.lookup("config5", "bwd") or {})}
+           "launch_fwd": dict(autotune.lookup(ds, cams, "fwd") or {}),
+           "launch_bwd": dict(autotune.lookup(ds, cams, "bwd") or {})}
     del gs, gd, gt, ds
     torch.cuda.empty_cache()
     return res
@@ -317,8 +317,8 @@ def bench_config2(scene, cams, dev, args, timed, oracle2):
     ds, perm, inv = voro.voro_morton_reorder(ds0)
     del ds0
     voro.voro_prepare(ds)
-    params = autotune.params_for("shell100k", "fwd")
-    params_bwd = autotune.params_for("shell100k", "bwd")
+    params = autotune.params_for(ds, cams, "fwd")
+    params_bwd = autotune.params_for(ds, cams, "bwd")
     ccams = [voro.camera_of(c) for c in cams]
     rays_per_step = cams[0].n_rays * N_POSES
     npx = cams[0].n_pixels
@@ -514,7 +514,7 @@ def bench_config3(scene, dev, args, timed):
     tex = ds.texels.clone().requires_grad_(True)
     g = torch.from_numpy(synth.upstream(cam.n_rays, 3, with_gT=False)[0]).to(dev)
     ccam = [voro.camera_of(cam)]
-    pf, pb = autotune.params_for("config3", "fwd"), autotune.params_for("config3", "bwd")
+    pf, pb = autotune.params_for(ds, [cam], "fwd"), autotune.params_for(ds, [cam], "bwd")
 
     def reset():
         sites.grad = None

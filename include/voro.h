@@ -233,8 +233,10 @@ voro_status voro_default_params(voro_params* p);
  * (16 B per adjacency entry: (p_j - p_i)/|p_j - p_i|^2 and j, stored at the
  * adjacency's own offsets with no padding, so M records), their binary16
  * copies (8 B per entry, for the edge_fp16 variant), the nearest-site
- * search's partial results and the persistent launch's work counters.
- * Host-only; needs no device.
+ * search's partial results, the persistent launch's work counters and the
+ * adjoint's per-cell gradient accumulator (16 B per cell; cleared by
+ * voro_prepare and left clear by every adjoint call).  Host-only; needs no
+ * device.
  */
 voro_status voro_workspace_size(const voro_scene* scene, size_t* bytes);
 
@@ -299,11 +301,15 @@ voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_b
  * (+ g_dist[r] L_dist[r]).
  * Replays each ray's walk (same code, same cell sequence) and recovers the
  * back-to-front colour suffix from the saved forward totals rgb and T, so
- * nothing per step is stored between the passes.  Accumulates (+=, FP32
- * atomics) into
+ * nothing per step is stored between the passes.  Accumulates (+=) into
  *   g_sites [N,3], g_density [N] (dL/dsigma), g_texels [N,R,R,4] float
  *   ([N,2,R,R,4] with tex_maps = 2; A channel untouched), whatever the
- *   texel storage type.
+ *   texel storage type.  Texel gradients are added with FP32 atomics;
+ *   position and density gradients are first summed (FP32 atomics) into the
+ *   workspace's per-cell accumulator, which a second kernel on the same
+ *   stream adds into g_sites / g_density and clears again, so the
+ *   workspace is written: no other call may use it until the stream has
+ *   passed this one.
  * g_T may be NULL (zero).  dist [R,3] (voro_render_fwd's output) and g_dist
  * [R] add L += sum_r g_dist[r] dist[r,0]; both NULL or both given.
  * params.skip_w must be 0.  Gradients reach site
@@ -311,7 +317,7 @@ voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_b
  * appearance 1, through the surface direction x - p_i (x moving with the
  * crossing that places it); tmax, early termination and max_steps pass none.
  */
-voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_bytes,
+voro_status voro_render_bwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                             const float* o, const float* d, const float* tmax,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
                             const float* rgb, const float* T, const float* g_rgb,

@@ -1,24 +1,35 @@
 """Launch-shape autotuner for the walk kernels.
 
-Picks, per workload and direction (forward / adjoint), the number of lanes
-that share a ray's neighbour tests (rays per wave = 64 / lanes), the screen
-tile a wave walks, the workgroup size and the schedule (grid or persistent
-queue), by timing the multi-view launch with HIP events on the caller's
-device.  Results live in
-``autotune_table.json`` next to this file; ``lookup`` returns the tuned
-``voro_params`` fields (or None).
+Picks, per workload class and direction (forward / adjoint), the number of
+lanes that share a ray's neighbour tests (rays per wave = 64 / lanes), the
+screen tile a wave walks, the workgroup size and the schedule (grid,
+persistent queue or lane refill), by timing the multi-view launch with HIP
+events on the caller's device.
+
+A workload class is keyed by what changes the best launch: the scene size
+(rounded up to a power of two), the texture resolution, the texel storage
+type and the set of camera models in the launch.  Results live in
+``autotune_table.json`` next to this file.  ``lookup`` returns the tuned
+fields for the exact class, or else for the tuned class with the same
+texture, texel type, camera set and direction and the nearest scene size,
+or else None (the library's defaults then apply).
 
     python -m paper_2608_17682_amd.autotune shell100k [config3] [config5]
 """
 from __future__ import annotations
 
 import json
+import math
 import os
 import sys
 import time
 from typing import Dict, Iterable, List, Optional
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table.json")
+LAUNCH_FIELDS = ("lanes_per_ray", "tile_w", "tile_h", "block", "schedule")
+MODEL_NAMES = {0: "pinhole", 1: "fisheye", 2: "rolling_shutter", 3: "thin_lens",
+               4: "motion_blur"}
+DTYPE_NAMES = {0: "f32", 1: "f16", 2: "bf16"}
 
 
 def candidates() -> List[dict]:
@@ -39,6 +50,26 @@ def candidates() -> List[dict]:
     return out
 
 
+def size_bucket(n_sites: int) -> int:
+    """Scene size rounded up to a power of two."""
+    return 1 << max(0, int(math.ceil(math.log2(max(1, int(n_sites))))))
+
+
+def workload_key(n_sites: int, tex_res: int, tex_dtype: int, models, direction: str) -> str:
+    """Table key of a workload class, e.g. 'n4194304|r8|f16|fisheye+pinhole|bwd'."""
+    mix = "+".join(sorted(MODEL_NAMES[int(m)] for m in set(int(m) for m in models)))
+    return f"n{size_bucket(n_sites)}|r{int(tex_res)}|{DTYPE_NAMES[int(tex_dtype)]}|{mix}|{direction}"
+
+
+def _models(cams) -> List[int]:
+    return [int(c.model) for c in cams]
+
+
+def key_of(ds, cams, direction: str) -> str:
+    """Key of a prepared DeviceScene and its cameras."""
+    return workload_key(ds.n, ds.tex_res, ds.tex_dtype, _models(cams), direction)
+
+
 def _load() -> Dict[str, dict]:
     if os.path.exists(TABLE):
         with open(TABLE) as f:
@@ -46,18 +77,32 @@ def _load() -> Dict[str, dict]:
     return {}
 
 
-def lookup(workload: str, direction: str) -> Optional[dict]:
-    """Tuned launch fields for (workload, 'fwd' | 'bwd'), or None."""
-    e = _load().get(f"{workload}|{direction}")
-    if not e:
-        return None
-    return {k: e[k] for k in ("lanes_per_ray", "tile_w", "tile_h", "block", "schedule") if k in e}
+def lookup_key(key: str, table: Optional[Dict[str, dict]] = None) -> Optional[dict]:
+    """Tuned launch fields for a key: exact, else the nearest scene size with the
+    same texture, texel type, camera set and direction, else None."""
+    table = _load() if table is None else table
+    e = table.get(key)
+    if e is None:
+        n, rest = key.split("|", 1)
+        target = math.log2(int(n[1:]))
+        near = [(abs(math.log2(int(k.split("|", 1)[0][1:])) - target), k)
+                for k in table if k.split("|", 1)[1] == rest]
+        if not near:
+            return None
+        e = table[min(near)[1]]
+    return {k: e[k] for k in LAUNCH_FIELDS if k in e}
 
 
-def params_for(workload: str, direction: str):
+def lookup(ds, cams, direction: str) -> Optional[dict]:
+    """Tuned launch fields for (scene, cameras, 'fwd' | 'bwd'), or None."""
+    return lookup_key(key_of(ds, cams, direction))
+
+
+def params_for(ds, cams, direction: str):
+    """voro_params with the library defaults and the tuned launch shape (if any)."""
     from . import voro
     p = voro.default_params()
-    t = lookup(workload, direction)
+    t = lookup(ds, cams, direction)
     if t:
         for k, v in t.items():
             setattr(p, k, v)
@@ -80,7 +125,7 @@ def _time(fn, reps: int, warmup: int = 1) -> float:
 
 
 def tune(ds, cams, reps: int = 3, cands: Iterable[dict] = None, log=print) -> Dict[str, dict]:
-    """Time every candidate on the persistent launch over `cams` (prepared
+    """Time every candidate on the multi-view launch over `cams` (prepared
     DeviceScene `ds`); returns {'fwd': best, 'bwd': best} with times in ms."""
     import torch
     from . import synth, voro
@@ -160,7 +205,7 @@ def main(argv):
         ds, cams = _workload(n)
         best = tune(ds, cams, log=lambda m: print(f"{n}: {m}", flush=True))
         for direction, e in best.items():
-            table[f"{n}|{direction}"] = e
+            table[key_of(ds, cams, direction)] = dict(e, tuned_on=n)
         print(f"{n}: tuned in {time.perf_counter() - t0:.1f}s", flush=True)
         del ds
     out = os.environ.get("VORO_AUTOTUNE_OUT", TABLE)

@@ -14,8 +14,9 @@
 
 namespace voro {
 
-voro_status launch_locate_brute(const voro_scene* scene, const void* ws, const float* origins,
+voro_status launch_locate_brute(const voro_scene* scene, void* partials, const float* origins,
                                 int U, int32_t* out, hipStream_t st);
+float4* cell_grads(const voro_scene* s, void* ws);
 
 // ------------------------------------------------------------- gen_rays
 __global__ void __launch_bounds__(256) k_gen_rays(CamTable ct, float* __restrict__ o,
@@ -179,7 +180,7 @@ __device__ __forceinline__ void write_ray_out(const ViewsArgs& a, const TileRay&
 // hardware dispatcher balances the load.  One lane per ray walks with staged
 // edge rows (dynamic LDS: kStageBytesPerWave per wave) unless the edges are
 // ranked in half precision.
-template <int LPR, int TEX, int APP, bool PERSIST>
+template <int LPR, int TEX, int APP, bool PERSIST, bool E16>
 __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
   extern __shared__ float4 slabs[];
   const int lane = threadIdx.x & 63;
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
       break;
     }
     TileRay tr;
-    if (LPR == 1 && !a.w.edge16) {
+    if constexpr (LPR == 1 && !E16) {
       const bool has = tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr);
       RayIn r{};
       if (has) {
@@ -210,11 +211,15 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
       const RayOut out = walk_forward_staged<TEX, APP>(
           a.s, a.w, r, has, lane, slabs + wave * (kStageBytesPerWave / 16), nullptr, 0, cnt);
       if (has) write_ray_out<LPR>(a, tr, out);
-    } else if (tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr)) {
+    } else {
+      if (!tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr)) {
+        if constexpr (!PERSIST) break;
+        continue;
+      }
       bool capped = false;
       const RayIn r = views_ray(a, tr, &capped);
       capped_n += capped ? 1u : 0u;
-      const RayOut out = walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, nullptr, 0, cnt);
+      const RayOut out = walk_forward<LPR, TEX, APP, E16>(a.s, a.w, r, sub, nullptr, 0, cnt);
       if (sub == 0) write_ray_out<LPR>(a, tr, out);
     }
     if constexpr (!PERSIST) break;
@@ -235,7 +240,7 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
 constexpr int kRefillMin = 16;
 constexpr int kStripTiles = 4;  // 256 rays per wave
 
-template <int TEX, int APP>
+template <int TEX, int APP, bool E16>
 __global__ void __launch_bounds__(256) k_views_fwd_refill(ViewsArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -272,7 +277,7 @@ __global__ void __launch_bounds__(256) k_views_fwd_refill(ViewsArgs a) {
         if (q >= pool) break;
         continue;
       }
-      if (active && fwd_step<1, TEX, APP>(st, a.s, a.w, r, 0, nullptr, 0, cnt, false)) {
+      if (active && fwd_step<1, TEX, APP, E16>(st, a.s, a.w, r, 0, nullptr, 0, cnt, false)) {
         write_ray_out<1>(a, tr, fwd_end<APP>(st, true, cnt));
         active = false;
       }
@@ -300,15 +305,17 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   const int unit_w = a.tile_w * wx;
   const int unit_h = a.tile_h * (nwaves / wx);
   const int RR = a.s.res * a.s.res;
-  __shared__ int s_keys[kTableCap];
-  __shared__ float s_vals[16 * kTableCap];
+  constexpr int kCap = TableShape<APP>::cap;
+  constexpr int kOb = TableShape<APP>::outbox;
+  __shared__ int s_keys[kCap];
+  __shared__ float s_vals[16 * kCap];
   __shared__ int s_unit;
-  __shared__ int s_okeys[4][kOutbox];
-  __shared__ float s_ovals[4][kStageStride * kOutbox];
-  GradTable tab;
+  __shared__ int s_okeys[4][kOb];
+  __shared__ float s_ovals[4][kStageStride * kOb];
+  GradTable<kCap> tab;
   tab.keys = s_keys;
   tab.vals = s_vals;
-  const Outbox ob{s_okeys[wave], s_ovals[wave]};
+  const Outbox ob{s_okeys[wave], s_ovals[wave], kOb};
   table_clear(tab);
   Counters cnt;
   int probe = 0;
@@ -422,7 +429,7 @@ static size_t fwd_lds(int block) {
   return LPR == 1 ? (size_t)(block / 64) * kStageBytesPerWave : 0;
 }
 
-template <int LPR, int TEX, int APP>
+template <int LPR, int TEX, int APP, bool E16 = false>
 static int persistent_blocks(bool backward, int block) {
   static int cached[2][3] = {};
   int& c = cached[backward ? 1 : 0][block == 64 ? 0 : (block == 128 ? 1 : 2)];
@@ -432,13 +439,13 @@ static int persistent_blocks(bool backward, int block) {
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if constexpr (APP == 2) {
     (void)backward;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block,
-                                                       fwd_lds<LPR>(block));
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true, E16>,
+                                                       block, fwd_lds<LPR>(block));
   } else if (backward) {
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_bwd<LPR, TEX, APP, true>, block, 0);
   } else {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true>, block,
-                                                       fwd_lds<LPR>(block));
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_views_fwd<LPR, TEX, APP, true, E16>,
+                                                       block, fwd_lds<LPR>(block));
   }
   (void)hipGetLastError();
   c = max(kXcd, max(1, cus) * max(1, occ));
@@ -446,43 +453,51 @@ static int persistent_blocks(bool backward, int block) {
   return c;
 }
 
-template <int LPR, int TEX, int APP>
-static void launch_views_t(bool backward, bool persist, const ViewsArgs& a, int block,
-                           hipStream_t st) {
+// forward launches: lane refill, persistent queue or grid
+template <int LPR, int TEX, int APP, bool E16>
+static void launch_views_fwd_t(bool persist, const ViewsArgs& a, int block, hipStream_t st) {
   const int nwaves = block / 64;
   if constexpr (LPR == 1) {
-    if (!backward && a.strip_tiles > 0) {
+    if (a.strip_tiles > 0) {
       const int strips = a.strip_off[a.ct.V];
-      hipLaunchKernelGGL((k_views_fwd_refill<TEX, APP>), dim3(max(1, (strips + nwaves - 1) / nwaves)),
-                         dim3(block), 0, st, a);
+      hipLaunchKernelGGL((k_views_fwd_refill<TEX, APP, E16>),
+                         dim3(max(1, (strips + nwaves - 1) / nwaves)), dim3(block), 0, st, a);
       return;
     }
   }
-  if constexpr (APP == 2) {
-    // forward only: the comparison model has no adjoint (refused on the host)
-    if (persist) {
-      const int blocks = persistent_blocks<LPR, TEX, APP>(false, block);
-      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block),
-                         fwd_lds<LPR>(block), st, a);
-    } else {
-      const int blocks = max(1, (a.total_tiles + nwaves - 1) / nwaves);
-      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block),
-                         fwd_lds<LPR>(block), st, a);
-    }
-  } else if (persist) {
-    const int blocks = persistent_blocks<LPR, TEX, APP>(backward, block);
-    if (backward)
-      hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block),
-                         fwd_lds<LPR>(block), st, a);
-  } else if (backward) {
-    hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, false>), dim3(max(1, a.total_tiles)), dim3(block),
-                       0, st, a);
+  if (persist) {
+    const int blocks = persistent_blocks<LPR, TEX, APP, E16>(false, block);
+    hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, true, E16>), dim3(blocks), dim3(block),
+                       fwd_lds<LPR>(block), st, a);
   } else {
     const int blocks = max(1, (a.total_tiles + nwaves - 1) / nwaves);
-    hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block),
+    hipLaunchKernelGGL((k_views_fwd<LPR, TEX, APP, false, E16>), dim3(blocks), dim3(block),
                        fwd_lds<LPR>(block), st, a);
+  }
+}
+
+template <int LPR, int TEX, int APP>
+static void launch_views_t(bool backward, bool persist, const ViewsArgs& a, int block,
+                           hipStream_t st) {
+  if (!backward) {
+    if constexpr (LPR == 1) {
+      if (a.w.edge16) {
+        launch_views_fwd_t<1, TEX, APP, true>(persist, a, block, st);
+        return;
+      }
+    }
+    launch_views_fwd_t<LPR, TEX, APP, false>(persist, a, block, st);
+    return;
+  }
+  if constexpr (APP != 2) {
+    // (the comparison model of appearance 2 has no adjoint: refused on the host)
+    if (persist) {
+      const int blocks = persistent_blocks<LPR, TEX, APP>(true, block);
+      hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
+    } else {
+      hipLaunchKernelGGL((k_views_bwd<LPR, TEX, APP, false>), dim3(max(1, a.total_tiles)),
+                         dim3(block), 0, st, a);
+    }
   }
 }
 
@@ -508,13 +523,47 @@ static void launch_views_tex(int tex, int lpr, bool backward, bool persist, cons
   }
 }
 
-static voro_status views_common(bool backward, const voro_scene* scene, void* ws, size_t ws_bytes,
+// Scratch of a multi-view launch: the tile-queue counters, the camera
+// centres and their cells, and the brute-force search's partial results.
+constexpr size_t kViewsScratchCounters = 0;
+constexpr size_t kViewsScratchCenters = 256;
+constexpr size_t kViewsScratchOrigins = 512;
+constexpr size_t kViewsScratchPartials = 768;
+constexpr size_t kViewsScratchBytes =
+    kViewsScratchPartials + (size_t)VORO_MAX_VIEWS * kLocateChunks * 16;
+static_assert(kViewsScratchCenters >= kXcd * 4 && kViewsScratchOrigins - kViewsScratchCenters >=
+              VORO_MAX_VIEWS * 4 && kViewsScratchPartials - kViewsScratchOrigins >=
+              3 * VORO_MAX_VIEWS * 4, "views scratch layout");
+
+// Where a launch keeps its scratch: counters, centres and their cells at
+// `base` (kViewsScratchPartials bytes), the partial results at `partials`.
+struct ViewsScratch {
+  char* base;
+  void* partials;
+};
+
+// static_scratch null: the scratch lives in the workspace (counter region and
+// the nearest-site search's region), which must then hold voro_workspace_size
+// bytes; otherwise the workspace is only read and must hold the prepared
+// records.
+static voro_status views_common(bool backward, const voro_scene* scene, const void* ws,
+                                size_t ws_bytes, const ViewsScratch* static_scratch,
                                 const voro_camera* cams, int32_t V, const voro_params* params,
                                 ViewsArgs& a, int64_t* n_rays, int64_t* n_pixels, bool* any_spp,
                                 void* stream) {
   voro_status st;
   if ((st = check_scene(scene)) != VORO_OK) return st;
-  if ((st = check_ws(scene, ws, ws_bytes)) != VORO_OK) return st;
+  static_assert(kViewsScratchPartials <= 4096, "counter region");
+  const WsLayout W = ws_layout(scene->n_sites, scene->n_edges);
+  const size_t ws_needed = static_scratch ? W.locate : W.total;
+  if (!ws) return fail(VORO_EWORKSPACE, "workspace is NULL");
+  if (!aligned(ws, 256)) return fail(VORO_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < ws_needed)
+    return fail(VORO_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, ws_needed);
+  const ViewsScratch sc = static_scratch
+      ? *static_scratch
+      : ViewsScratch{(char*)const_cast<void*>(ws) + W.counters,
+                     (char*)const_cast<void*>(ws) + W.locate};
   if ((st = check_params(params, backward)) != VORO_OK) return st;
   if ((st = check_appearance(scene, params)) != VORO_OK) return st;
   if ((st = check_cameras(cams, V, n_rays, n_pixels)) != VORO_OK) return st;
@@ -523,11 +572,9 @@ static voro_status views_common(bool backward, const voro_scene* scene, void* ws
   *any_spp = spp;
   if ((st = check_device()) != VORO_OK) return st;
   const Launch L = resolve_launch(params);
-  const WsLayout W = ws_layout(scene->n_sites, scene->n_edges);
-  char* base = (char*)ws + W.counters;
-  a.counters = reinterpret_cast<unsigned int*>(base);
-  int32_t* centers = reinterpret_cast<int32_t*>(base + 256);
-  float* origins = reinterpret_cast<float*>(base + 512);
+  a.counters = reinterpret_cast<unsigned int*>(sc.base + kViewsScratchCounters);
+  int32_t* centers = reinterpret_cast<int32_t*>(sc.base + kViewsScratchCenters);
+  float* origins = reinterpret_cast<float*>(sc.base + kViewsScratchOrigins);
   a.center_cell = centers;
   a.s = dev_scene(scene, ws);
   a.w = walk_params(params);
@@ -549,7 +596,7 @@ static voro_status views_common(bool backward, const voro_scene* scene, void* ws
   }
   hipLaunchKernelGGL(k_views_setup, dim3(1), dim3(64), 0, s, cc, origins, 3 * V, a.counters);
   if ((st = check_launch("views: setup")) != VORO_OK) return st;
-  if ((st = launch_locate_brute(scene, ws, origins, V, centers, s)) != VORO_OK) return st;
+  if ((st = launch_locate_brute(scene, sc.partials, origins, V, centers, s)) != VORO_OK) return st;
   const int block = L.block;
   // the refill schedule drives the one-lane-per-ray forward; the adjoint
   // (whose work unit is a workgroup tile) takes the persistent queue then
@@ -615,7 +662,8 @@ voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_b
   for (int v = 0; v < V; ++v)
     if (cams[v].spp > 1 && !ray_rgbT)
       return fail(VORO_EINVAL, "ray_rgbT is required when a view has spp > 1");
-  st = views_common(false, scene, ws, ws_bytes, cams, V, params, a, &nr, &np, &any_spp, stream);
+  st = views_common(false, scene, ws, ws_bytes, nullptr, cams, V, params, a, &nr, &np, &any_spp,
+                    stream);
   if (st != VORO_OK) return st;
   if (any_spp) {
     const int n = (int)np;
@@ -649,13 +697,15 @@ voro_status voro_render_views_bwd(const voro_scene* scene, void* ws, size_t ws_b
   a.ray_rgbT_in = ray_rgbT;
   a.g_rgb = g_rgb;
   a.g_T = g_T;
-  a.g.sites = g_sites;
-  a.g.density = g_density;
   a.g.texels = g_texels;
   a.g.maps = scene && scene->tex_maps == 2 ? 2 : 1;
   a.stats = reinterpret_cast<unsigned long long*>(stats);
+  if (scene && ws) a.g.cell = cell_grads(scene, ws);
   bool any_spp = false;
-  return views_common(true, scene, ws, ws_bytes, cams, V, params, a, &nr, &np, &any_spp, stream);
+  st = views_common(true, scene, ws, ws_bytes, nullptr, cams, V, params, a, &nr, &np, &any_spp,
+                    stream);
+  if (st != VORO_OK) return st;
+  return launch_fold_cell_grads(scene, ws, g_sites, g_density, (hipStream_t)stream);
 }
 
 }  // extern "C"

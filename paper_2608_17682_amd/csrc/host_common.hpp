@@ -22,12 +22,13 @@ voro_status fail(voro_status st, const char* fmt, ...);
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace layout: cell records, edge records (FP32, then a half copy of the
-// edge vectors), nearest-site partials,
-// persistent-launch counters and per-view start cells.
+// edge vectors), nearest-site partials, persistent-launch counters and
+// per-view start cells, and the adjoint's per-cell accumulator of position
+// and density gradients (one float4 per cell, zero between adjoint calls).
 constexpr int kLocateBruteMax = 64;    // origins searched by brute force
 constexpr int kLocateChunks = 256;     // max partial results per origin
 struct WsLayout {
-  size_t cells, edges, edges16, locate, counters, total;
+  size_t cells, edges, edges16, locate, counters, cellg, total;
 };
 
 inline WsLayout ws_layout(int32_t n, int64_t m) {
@@ -37,9 +38,15 @@ inline WsLayout ws_layout(int32_t n, int64_t m) {
   L.edges16 = align256(L.edges + (size_t)m * 16);
   L.locate = align256(L.edges16 + (size_t)m * 8 + 16);
   L.counters = align256(L.locate + (size_t)kLocateBruteMax * kLocateChunks * 16);
-  L.total = align256(L.counters + 4096);
+  L.cellg = align256(L.counters + 4096);
+  L.total = align256(L.cellg + (size_t)n * 16);
   return L;
 }
+
+// adds the workspace's per-cell accumulator into g_sites / g_density and
+// clears it (stream-ordered after an adjoint kernel; defined in walk.hip)
+voro_status launch_fold_cell_grads(const voro_scene* scene, void* ws, float* g_sites,
+                                   float* g_density, hipStream_t st);
 
 voro_status check_scene(const voro_scene* s);
 voro_status check_ws(const voro_scene* s, const void* ws, size_t ws_bytes);

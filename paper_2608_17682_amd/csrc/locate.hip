@@ -129,11 +129,11 @@ __global__ void __launch_bounds__(256) k_locate_walk(DevScene s, const float* __
   }
 }
 
-// Brute-force nearest sites of U <= kLocateBruteMax origins into out (device).
-voro_status launch_locate_brute(const voro_scene* scene, const void* ws, const float* origins,
+// Brute-force nearest sites of U <= kLocateBruteMax origins into out (device);
+// partials: U * kLocateChunks * 16 bytes of device scratch.
+voro_status launch_locate_brute(const voro_scene* scene, void* partials, const float* origins,
                                 int U, int32_t* out, hipStream_t st) {
-  const WsLayout L = ws_layout(scene->n_sites, scene->n_edges);
-  BestD* partial = reinterpret_cast<BestD*>((char*)ws + L.locate);
+  BestD* partial = reinterpret_cast<BestD*>(partials);
   int chunks = (scene->n_sites + 4095) / 4096;
   chunks = max(1, min(chunks, kLocateChunks));
   hipLaunchKernelGGL(k_locate_brute, dim3(chunks, U), dim3(256), 0, st, scene->sites,
@@ -158,7 +158,11 @@ extern "C" voro_status voro_locate_origins(const voro_scene* scene, const void* 
   if (!origins || !cell_out) return fail(VORO_EINVAL, "origins and cell_out must not be NULL");
   if ((st = check_device()) != VORO_OK) return st;
   const hipStream_t s = (hipStream_t)stream;
-  if (!hint && U <= kLocateBruteMax) return launch_locate_brute(scene, ws, origins, U, cell_out, s);
+  if (!hint && U <= kLocateBruteMax) {
+    const WsLayout L = ws_layout(scene->n_sites, scene->n_edges);
+    // the partials' region of the workspace is scratch (const only in the signature)
+    return launch_locate_brute(scene, (char*)const_cast<void*>(ws) + L.locate, origins, U, cell_out, s);
+  }
   const DevScene d = dev_scene(scene, ws);
   hipLaunchKernelGGL(k_locate_walk, dim3((U + 255) / 256), dim3(256), 0, s, d, origins, hint, U,
                      cell_out, reinterpret_cast<unsigned long long*>(stats));

@@ -154,54 +154,93 @@ __device__ __forceinline__ Best exit_search(const float4* __restrict__ edges, in
 }
 
 // ---- half-precision ranking (inference variant, Sec. 5.6 "fp16 edge
-// vectors").  The same u from binary16 copies of m; two records per 16-byte
-// load, one 8-byte load first when the row starts on an odd slot.  Returns
-// the best u's slot index (not the neighbour id) in j1, halved values.
-__device__ __forceinline__ float cross_u16(unsigned xy, unsigned z0, float q2x, float q2y,
-                                           float q2z, float dx, float dy, float dz) {
+// vectors"): the same u from binary16 copies of m, two records per 16-byte
+// load (one 8-byte load first when the row starts on an odd slot), with a
+// bound on how far each face's u can lie from the u that the FP32 record
+// gives.  With M = max |m16_c|, Q = |2q|_1, W = |w|_1 and the binary16
+// rounding of m at most 2^-11 |m| per component:
+//   |b32 - b16| <= Eb = 2^-10 M W,   |a32 - a16| <= Ea = 2^-10 M Q + 2^-21
+// (the FP32 roundings of both sides are inside the doubled constants), so
+// a face with b16 > 2 Eb certainly lies ahead, one with b16 <= -Eb certainly
+// does not, and for the first kind
+//   |u32 - u16| <= e = 2 (Ea + |u16| Eb) / b16 + 2^-20 |u16|
+// (the last term for the approximate reciprocals).  Anything else (a face
+// too close to parallel, a record out of the binary16 range) is `unsure`.
+struct Rank16 {
+  float lo1;   // smallest lower bound u16 - e
+  int k1;      // its slot in the row
+  float lo2;   // second smallest lower bound
+  float hi;    // smallest upper bound u16 + e
+  bool unsure;
+};
+
+__device__ __forceinline__ void rank16_push(Rank16& r, unsigned xy, unsigned z0, float q2x,
+                                            float q2y, float q2z, float dx, float dy, float dz,
+                                            float cQ, float cW, int k) {
   const float mx = (float)__builtin_bit_cast(_Float16, (uint16_t)(xy & 0xffffu));
   const float my = (float)__builtin_bit_cast(_Float16, (uint16_t)(xy >> 16));
   const float mz = (float)__builtin_bit_cast(_Float16, (uint16_t)(z0 & 0xffffu));
   const float b = dot3(mx, my, mz, dx, dy, dz);
   const float a = fmaf(-mz, q2z, fmaf(-my, q2y, fmaf(-mx, q2x, 1.0f)));
-  return b > 0.0f ? a * __builtin_amdgcn_rcpf(b) : kInf;
+  const float M = fmaxf(fabsf(mx), fmaxf(fabsf(my), fabsf(mz)));
+  const float Eb = M * cW;
+  const float Ea = fmaf(M, cQ, 0x1p-21f);
+  const bool ahead = b > 2.0f * Eb;        // false for NaN / inf records too
+  const bool behind = b <= -Eb;
+  r.unsure = r.unsure || !(ahead || behind);
+  if (ahead) {
+    const float rb = __builtin_amdgcn_rcpf(b);
+    const float u = a * rb;
+    const float au = fabsf(u);
+    const float e = fmaf(au, 0x1p-20f, 2.0f * fmaf(au, Eb, Ea) * rb);
+    const float lo = u - e;
+    r.hi = fminf(r.hi, u + e);
+    const bool lt = lo < r.lo1;
+    r.lo2 = __builtin_amdgcn_fmed3f(r.lo1, r.lo2, lo);
+    r.lo1 = lt ? lo : r.lo1;
+    r.k1 = lt ? k : r.k1;
+  }
 }
 
-__device__ __forceinline__ Best exit_search16(const uint2* __restrict__ edges16, int off, int deg,
-                                              float qx, float qy, float qz, float dx, float dy,
-                                              float dz) {
+// The slot that certainly holds the row's smallest FP32 crossing offset
+// (doubled), or -1 when the half-precision bounds cannot tell.
+__device__ __forceinline__ Rank16 rank16(const uint2* __restrict__ edges16, int off, int deg,
+                                         float qx, float qy, float qz, float dx, float dy,
+                                         float dz) {
   const float q2x = 2.0f * qx, q2y = 2.0f * qy, q2z = 2.0f * qz;
-  Best r;
-  r.t1 = kInf;
-  r.j1 = -1;
-  r.t2 = kInf;
+  const float cQ = 0x1p-10f * (fabsf(q2x) + fabsf(q2y) + fabsf(q2z));
+  const float cW = 0x1p-10f * (fabsf(dx) + fabsf(dy) + fabsf(dz));
+  Rank16 r;
+  r.lo1 = kInf;
+  r.k1 = -1;
+  r.lo2 = kInf;
+  r.hi = kInf;
+  r.unsure = false;
   const uint2* e = edges16 + off;
   int k = 0;
   if ((off & 1) && deg > 0) {
     const uint2 h = e[0];
-    best_push(r, cross_u16(h.x, h.y, q2x, q2y, q2z, dx, dy, dz), 0);
+    rank16_push(r, h.x, h.y, q2x, q2y, q2z, dx, dy, dz, cQ, cW, 0);
     k = 1;
   }
   for (; k + 4 <= deg; k += 4) {
     const uint4 A = *reinterpret_cast<const uint4*>(e + k);
     const uint4 B = *reinterpret_cast<const uint4*>(e + k + 2);
-    best_push(r, cross_u16(A.x, A.y, q2x, q2y, q2z, dx, dy, dz), k);
-    best_push(r, cross_u16(A.z, A.w, q2x, q2y, q2z, dx, dy, dz), k + 1);
-    best_push(r, cross_u16(B.x, B.y, q2x, q2y, q2z, dx, dy, dz), k + 2);
-    best_push(r, cross_u16(B.z, B.w, q2x, q2y, q2z, dx, dy, dz), k + 3);
+    rank16_push(r, A.x, A.y, q2x, q2y, q2z, dx, dy, dz, cQ, cW, k);
+    rank16_push(r, A.z, A.w, q2x, q2y, q2z, dx, dy, dz, cQ, cW, k + 1);
+    rank16_push(r, B.x, B.y, q2x, q2y, q2z, dx, dy, dz, cQ, cW, k + 2);
+    rank16_push(r, B.z, B.w, q2x, q2y, q2z, dx, dy, dz, cQ, cW, k + 3);
   }
   if (k + 2 <= deg) {
     const uint4 A = *reinterpret_cast<const uint4*>(e + k);
-    best_push(r, cross_u16(A.x, A.y, q2x, q2y, q2z, dx, dy, dz), k);
-    best_push(r, cross_u16(A.z, A.w, q2x, q2y, q2z, dx, dy, dz), k + 1);
+    rank16_push(r, A.x, A.y, q2x, q2y, q2z, dx, dy, dz, cQ, cW, k);
+    rank16_push(r, A.z, A.w, q2x, q2y, q2z, dx, dy, dz, cQ, cW, k + 1);
     k += 2;
   }
   if (k < deg) {
     const uint2 h = e[k];
-    best_push(r, cross_u16(h.x, h.y, q2x, q2y, q2z, dx, dy, dz), k);
+    rank16_push(r, h.x, h.y, q2x, q2y, q2z, dx, dy, dz, cQ, cW, k);
   }
-  r.t1 *= 0.5f;
-  r.t2 *= 0.5f;
   return r;
 }
 

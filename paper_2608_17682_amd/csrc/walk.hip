@@ -29,6 +29,7 @@ struct PrepArgs {
   float4* cells;
   float4* edges;
   uint2* edges16;
+  float4* cellg;  // the adjoint's per-cell accumulator, cleared here
   unsigned long long* stats;
 };
 
@@ -49,6 +50,7 @@ __global__ void __launch_bounds__(256) k_prepare(PrepArgs a) {
     a.cells[2 * (size_t)i] = make_float4(px, py, pz, a.density[i]);
     a.cells[2 * (size_t)i + 1] = make_float4(__int_as_float(bad_row ? 0 : off),
                                              __int_as_float(deg), 0.0f, 0.0f);
+    a.cellg[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (bad_row && a.stats) atomicAdd(&a.stats[VORO_STAT_BAD_CSR], 1ull);
   }
   if (bad_row) return;
@@ -85,6 +87,35 @@ __global__ void __launch_bounds__(256) k_prepare(PrepArgs a) {
   }
 }
 
+// Adds the per-cell accumulator into the caller's position and density
+// gradients (+=) and clears it; cells the adjoint did not touch are skipped.
+__global__ void __launch_bounds__(256) k_fold_cell_grads(float4* __restrict__ acc, int n,
+                                                         float* __restrict__ g_sites,
+                                                         float* __restrict__ g_density) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 v = acc[i];
+  if (v.x == 0.0f && v.y == 0.0f && v.z == 0.0f && v.w == 0.0f) return;
+  g_sites[3 * i] += v.x;
+  g_sites[3 * i + 1] += v.y;
+  g_sites[3 * i + 2] += v.z;
+  g_density[i] += v.w;
+  acc[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+voro_status launch_fold_cell_grads(const voro_scene* scene, void* ws, float* g_sites,
+                                   float* g_density, hipStream_t st) {
+  const WsLayout L = ws_layout(scene->n_sites, scene->n_edges);
+  const int n = scene->n_sites;
+  hipLaunchKernelGGL(k_fold_cell_grads, dim3((n + 255) / 256), dim3(256), 0, st,
+                     reinterpret_cast<float4*>((char*)ws + L.cellg), n, g_sites, g_density);
+  return check_launch("adjoint: fold position and density gradients");
+}
+
+float4* cell_grads(const voro_scene* s, void* ws) {
+  return reinterpret_cast<float4*>((char*)ws + ws_layout(s->n_sites, s->n_edges).cellg);
+}
+
 // ------------------------------------------------------- explicit-ray launch
 struct RayArgs {
   DevScene s;
@@ -114,7 +145,7 @@ struct RayArgs {
 
 // One lane per ray walks with staged edge rows (dynamic LDS:
 // kStageBytesPerWave per wave) unless the edges are ranked in half precision.
-template <int LPR, int TEX, int APP>
+template <int LPR, int TEX, int APP, bool E16>
 __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
   extern __shared__ float4 slabs[];
   const int nwaves = blockDim.x >> 6;
@@ -125,7 +156,7 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int ray = map_ray<LPR>(a.map, lb, wave, nwaves, grp);
   Counters cnt;
-  const bool staged = LPR == 1 && !a.w.edge16;
+  constexpr bool staged = LPR == 1 && !E16;
   if (ray >= 0 || staged) {
     RayIn r{};
     if (ray >= 0) {
@@ -145,7 +176,7 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
         staged ? walk_forward_staged<TEX, APP>(a.s, a.w, r, ray >= 0, lane,
                                                slabs + wave * (kStageBytesPerWave / 16), rec,
                                                a.max_record, cnt, a.dist_out != nullptr)
-               : walk_forward<LPR, TEX, APP>(a.s, a.w, r, sub, rec, a.max_record, cnt,
+               : walk_forward<LPR, TEX, APP, E16>(a.s, a.w, r, sub, rec, a.max_record, cnt,
                                              a.dist_out != nullptr);
     if (ray >= 0 && sub == 0) {
       a.rgb[3 * (size_t)ray] = out.r;
@@ -201,14 +232,16 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
       u.gD = a.g_dist[ray];
     }
   }
-  __shared__ int s_keys[kTableCap];
-  __shared__ float s_vals[16 * kTableCap];
-  __shared__ int s_okeys[4][kOutbox];
-  __shared__ float s_ovals[4][kStageStride * kOutbox];
-  GradTable tab;
+  constexpr int kCap = TableShape<APP>::cap;
+  constexpr int kOb = TableShape<APP>::outbox;
+  __shared__ int s_keys[kCap];
+  __shared__ float s_vals[16 * kCap];
+  __shared__ int s_okeys[4][kOb];
+  __shared__ float s_ovals[4][kStageStride * kOb];
+  GradTable<kCap> tab;
   tab.keys = s_keys;
   tab.vals = s_vals;
-  const Outbox ob{s_okeys[wave], s_ovals[wave]};
+  const Outbox ob{s_okeys[wave], s_ovals[wave], kOb};
   table_clear(tab);
   __syncthreads();
   // all lanes take part: the gradient records are merged across the wave,
@@ -223,15 +256,20 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
 template <int LPR, int TEX, int APP>
 static void launch_ray_kernel(bool backward, const RayArgs& a, int blocks, int block,
                               hipStream_t st) {
-  if constexpr (APP == 2) {
-    // the spherical-harmonic comparison model has no adjoint (refused on the host)
-    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block),
-                       LPR == 1 ? (size_t)(block / 64) * kStageBytesPerWave : 0, st, a);
-  } else if (backward) {
+  if (!backward) {
+    const size_t lds = LPR == 1 ? (size_t)(block / 64) * kStageBytesPerWave : 0;
+    if constexpr (LPR == 1) {
+      if (a.w.edge16) {
+        hipLaunchKernelGGL((k_render_fwd<1, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP, false>), dim3(blocks), dim3(block), lds, st, a);
+    return;
+  }
+  if constexpr (APP != 2) {
+    // (the comparison model of appearance 2 has no adjoint: refused on the host)
     hipLaunchKernelGGL((k_render_bwd<LPR, TEX, APP>), dim3(blocks), dim3(block), 0, st, a);
-  } else {
-    hipLaunchKernelGGL((k_render_fwd<LPR, TEX, APP>), dim3(blocks), dim3(block),
-                       LPR == 1 ? (size_t)(block / 64) * kStageBytesPerWave : 0, st, a);
   }
 }
 
@@ -266,6 +304,8 @@ static void dispatch_ray_kernel(int app, int tex, int lpr, bool backward, const 
   else
     dispatch_tex<0>(tex, lpr, backward, a, blocks, block, st);
 }
+
+float4* cell_grads(const voro_scene* s, void* ws);
 
 DevScene dev_scene(const voro_scene* s, const void* ws) {
   const WsLayout L = ws_layout(s->n_sites, s->n_edges);
@@ -358,6 +398,7 @@ voro_status voro_prepare(const voro_scene* scene, void* ws, size_t ws_bytes, uin
   a.cells = reinterpret_cast<float4*>((char*)ws + L.cells);
   a.edges = reinterpret_cast<float4*>((char*)ws + L.edges);
   a.edges16 = reinterpret_cast<uint2*>((char*)ws + L.edges16);
+  a.cellg = reinterpret_cast<float4*>((char*)ws + L.cellg);
   a.stats = reinterpret_cast<unsigned long long*>(stats);
   const long threads = (long)scene->n_sites * 16;
   const int blocks = (int)((threads + 255) / 256);
@@ -384,7 +425,7 @@ voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_b
   return ray_launch(false, scene, ws, ws_bytes, o, d, tmax, start_cell, R, params, a, stream);
 }
 
-voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_bytes,
+voro_status voro_render_bwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                             const float* o, const float* d, const float* tmax,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
                             const float* rgb, const float* T, const float* g_rgb,
@@ -405,12 +446,14 @@ voro_status voro_render_bwd(const voro_scene* scene, const void* ws, size_t ws_b
   a.g_T = g_T;
   a.dist_in = dist;
   a.g_dist = g_dist;
-  a.g.sites = g_sites;
-  a.g.density = g_density;
   a.g.texels = g_texels;
   a.g.maps = scene && scene->tex_maps == 2 ? 2 : 1;
   a.stats = reinterpret_cast<unsigned long long*>(stats);
-  return ray_launch(true, scene, ws, ws_bytes, o, d, tmax, start_cell, R, params, a, stream);
+  if (scene && ws) a.g.cell = cell_grads(scene, ws);
+  voro_status st =
+      ray_launch(true, scene, ws, ws_bytes, o, d, tmax, start_cell, R, params, a, stream);
+  if (st != VORO_OK || R == 0) return st;
+  return launch_fold_cell_grads(scene, ws, g_sites, g_density, (hipStream_t)stream);
 }
 
 }  // extern "C"

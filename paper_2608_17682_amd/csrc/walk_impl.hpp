@@ -46,9 +46,13 @@ struct Upstream {
 // sums of w and w sbar over the earlier segments.
 __device__ __forceinline__ float dist_s(float t) { return t / (1.0f + t); }
 
+// Gradient targets of the adjoint kernels.  Position and density gradients
+// go to a per-cell accumulator in the workspace, dp in xyz and dsigma in w,
+// so that one 16-byte slot (one cache line) takes all four terms of a cell;
+// a second kernel then adds it into the caller's arrays.  Texel gradients go
+// straight to the caller's array.
 struct Grads {
-  float* sites;    // [N,3]
-  float* density;  // [N]
+  float4* cell;    // [N] workspace accumulator: (dp.x, dp.y, dp.z, dsigma)
   float* texels;   // [N,R,R,4], or [N,2,R,R,4] for the full appearance model
   int maps;        // texture maps per cell (1 or 2)
 };
@@ -76,8 +80,10 @@ __device__ __forceinline__ void flush_counters(Counters c, bool contribute, int 
 
 // One step of the walk: the exit of cell `cur` entered at t_in.  lrow: the
 // cell's edge row staged in LDS by the wave (one lane per ray), or null to
-// gather it from global memory.
-template <int LPR>
+// gather it from global memory.  E16: rank the row from its half-precision
+// copy first (a template switch, so the exact walk's kernels do not carry
+// that code's registers).
+template <int LPR, bool E16 = false>
 __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w, const RayIn& r,
                                           const Cell& c, int cur, float t_in, int sub,
                                           const float4* lrow = nullptr) {
@@ -85,16 +91,34 @@ __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w
   const float qy = fmaf(t_in, r.dy, r.oy) - c.py;
   const float qz = fmaf(t_in, r.dz, r.oz) - c.pz;
   Best b;
-  if (LPR == 1 && w.edge16) {
-    // rank in half precision; the winner's crossing and id come from its
-    // full-precision record, so agreeing decisions give the exact walk's
-    // numbers (near ties still go to the FP64 re-decision)
-    b = exit_search16(s.edges16, c.off, c.deg, qx, qy, qz, r.dx, r.dy, r.dz);
-    if (b.j1 >= 0) {
-      const float4 E = s.edges[c.off + b.j1];
-      b.t1 = 0.5f * cross_u(E, 2.0f * qx, 2.0f * qy, 2.0f * qz, r.dx, r.dy, r.dz);
-      b.j1 = __float_as_int(E.w);
+  bool searched = false;
+  if constexpr (LPR == 1 && E16) {
+    // Rank in half precision.  When the bounds leave a single face that can
+    // hold the smallest FP32 crossing, and every other face lies beyond the
+    // tie window from it, that face's FP32 record gives exactly what the
+    // FP32 search would (its crossing, its id, no FP64 re-decision);
+    // otherwise the row is searched in FP32.  Either way the walk is the
+    // exact walk.
+    const Rank16 h = rank16(s.edges16, c.off, c.deg, qx, qy, qz, r.dx, r.dy, r.dz);
+    if (!h.unsure && h.k1 >= 0 && h.lo2 > h.hi) {
+      const float4 E = s.edges[c.off + h.k1];
+      const float u = cross_u(E, 2.0f * qx, 2.0f * qy, 2.0f * qz, r.dx, r.dy, r.dz);
+      const float t1 = 0.5f * u;
+      const float win = w.tie_window * fmaxf(1.0f, fabsf(t_in + t1));
+      if (0.5f * h.lo2 - t1 > win) {
+        b.t1 = t1;
+        b.j1 = __float_as_int(E.w);
+        b.t2 = 0.5f * h.lo2;
+        searched = true;
+      }
+    } else if (!h.unsure && h.k1 < 0) {
+      b.t1 = kInf;  // no face lies ahead
+      b.j1 = -1;
+      b.t2 = kInf;
+      searched = true;
     }
+  }
+  if (searched) {
   } else if (LPR == 1 && lrow) {
     b = exit_search<1>(lrow, 0, c.deg, 0, qx, qy, qz, r.dx, r.dy, r.dz);
   } else {
@@ -156,7 +180,7 @@ __device__ __forceinline__ bool fwd_begin(FwdState<APP>& st, const DevScene& s, 
 
 // One visited cell (lrow: its edge row staged in LDS, or null); true when
 // the ray has ended.
-template <int LPR, int TEX, int APP>
+template <int LPR, int TEX, int APP, bool E16 = false>
 __device__ __forceinline__ bool fwd_step(FwdState<APP>& st, const DevScene& s,
                                          const WalkParams& w, const RayIn& r, int sub,
                                          int32_t* rec, int max_record, Counters& cnt,
@@ -164,7 +188,7 @@ __device__ __forceinline__ bool fwd_step(FwdState<APP>& st, const DevScene& s,
   const int cur = st.cur;
   const float t_in = st.t_in;
   const Cell c = load_cell(s.cells, cur);
-  const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub, lrow);
+  const Exit ex = step_exit<LPR, E16>(s, w, r, c, cur, t_in, sub, lrow);
   cnt.redecide += ex.redecided ? 1u : 0u;
   cnt.deg += (uint32_t)c.deg;
   const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
@@ -235,7 +259,7 @@ __device__ __forceinline__ RayOut fwd_end(const FwdState<APP>& st, bool walked, 
   return out;
 }
 
-template <int LPR, int TEX, int APP>
+template <int LPR, int TEX, int APP, bool E16 = false>
 __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkParams& w,
                                                const RayIn& r, int sub, int32_t* rec,
                                                int max_record, Counters& cnt,
@@ -243,7 +267,7 @@ __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkPara
   FwdState<APP> st;
   const bool walk = fwd_begin<APP>(st, s, r, cnt);
   if (walk)
-    while (!fwd_step<LPR, TEX, APP>(st, s, w, r, sub, rec, max_record, cnt, dist_on)) {
+    while (!fwd_step<LPR, TEX, APP, E16>(st, s, w, r, sub, rec, max_record, cnt, dist_on)) {
     }
   return fwd_end<APP>(st, walk, cnt);
 }
@@ -370,9 +394,10 @@ __device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const W
 // segments) go straight to the atomics.
 
 __device__ __forceinline__ void atomic_site(const Grads& g, int cell, float x, float y, float z) {
-  atomicAdd(&g.sites[3 * (size_t)cell], x);
-  atomicAdd(&g.sites[3 * (size_t)cell + 1], y);
-  atomicAdd(&g.sites[3 * (size_t)cell + 2], z);
+  float* p = reinterpret_cast<float*>(g.cell + cell);
+  atomicAdd(p, x);
+  atomicAdd(p + 1, y);
+  atomicAdd(p + 2, z);
 }
 
 // A record's key is (cell * maps + map) * R^2 + texel quad.  Address of term
@@ -382,8 +407,7 @@ __device__ __forceinline__ float* record_addr(const Grads& g, int key, int c, in
   const int cm = key / RR;
   const int base = key - cm * RR;
   const int cell = g.maps == 2 ? (cm >> 1) : cm;
-  if (c == 0) return g.density + cell;
-  if (c < 4) return g.sites + 3 * (size_t)cell + (c - 1);
+  if (c < 4) return reinterpret_cast<float*>(g.cell + cell) + (c == 0 ? 3 : c - 1);
   const int t = (c - 4) / 3;
   const int ch = (c - 4) - 3 * t;
   return g.texels + ((size_t)cm * (size_t)RR + (size_t)base) * 4 + (t & 1) * 4 + (t >> 1) * 4 * R +
@@ -392,14 +416,16 @@ __device__ __forceinline__ float* record_addr(const Grads& g, int key, int c, in
 
 // Per-wave LDS staging of records bound for global memory: 16 lanes then
 // write one record's 16 terms with one instruction, so a record costs about
-// four cache-line requests at the L2 atomic units instead of sixteen.  The
-// same area stages records bound for the workgroup table (see
-// emit_records), laid out [record][kStageStride].
-constexpr int kOutbox = 64;
+// four cache-line requests at the memory-side atomic units instead of
+// sixteen.  The area holds `cap` records; more senders go in turns.  With
+// the full appearance model the same area also stages the survivors bound
+// for the workgroup table (see emit_records), laid out [record][kStageStride],
+// and then holds a whole wave (64 records).
 constexpr int kStageStride = 17;  // odd: both access patterns spread over the banks
 struct Outbox {
-  int* keys;    // [kOutbox]
-  float* vals;  // [kStageStride * kOutbox]
+  int* keys;    // [cap]
+  float* vals;  // [kStageStride * cap]
+  int cap;
 };
 
 // Every lane of the wave must call this; `send` lanes hand over (key, v).
@@ -408,22 +434,26 @@ __device__ __forceinline__ void outbox_send(const Outbox& ob, bool send, int key
   const unsigned long long m = __ballot(send);
   if (m == 0ull) return;
   const int pos = __popcll(m & ((1ull << lane) - 1ull));
-  if (send) {
-    ob.keys[pos] = key;
+  const int total = __popcll(m);
+  const int cap = ob.cap;
+  for (int b0 = 0; b0 < total; b0 += cap) {
+    if (send && pos >= b0 && pos < b0 + cap) {
+      ob.keys[pos - b0] = key;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) ob.vals[c * kOutbox + pos] = v[c];
-  }
-  __builtin_amdgcn_wave_barrier();
-  const int n = __popcll(m);
-  for (int b = 0; b < n; b += 4) {
-    const int r = b + (lane >> 4);
-    const int c = lane & 15;
-    if (r < n) {
-      const float x = ob.vals[c * kOutbox + r];
-      if (x != 0.0f) atomicAdd(record_addr(g, ob.keys[r], c, RR, R), x);
+      for (int c = 0; c < 16; ++c) ob.vals[c * cap + pos - b0] = v[c];
     }
+    __builtin_amdgcn_wave_barrier();
+    const int n = min(cap, total - b0);
+    for (int b = 0; b < n; b += 4) {
+      const int r = b + (lane >> 4);
+      const int c = lane & 15;
+      if (r < n) {
+        const float x = ob.vals[c * cap + r];
+        if (x != 0.0f) atomicAdd(record_addr(g, ob.keys[r], c, RR, R), x);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
-  __builtin_amdgcn_wave_barrier();
 }
 
 // Workgroup gradient table in LDS: open addressing on the record key
@@ -432,71 +462,89 @@ __device__ __forceinline__ void outbox_send(const Outbox& ob, bool send, int key
 // added with LDS float atomics while the workgroup walks its rays; every
 // entry then reaches global memory once, when the workgroup flushes.  A
 // record that finds no slot within kTableProbes goes straight to global
-// memory.
-constexpr int kTableBits = 9;
-constexpr int kTableCap = 1 << kTableBits;
+// memory.  Capacity: as many entries as leave room for three workgroups
+// of four waves per CU (a larger table that costs a workgroup, or more
+// probes, measured slower; so did a smaller table with four workgroups).
 constexpr int kTableProbes = 8;
+constexpr int kTableCapSingle = 704;  // one texture map: 16-record outboxes beside it
+constexpr int kTableCapFull = 512;    // two maps: the outboxes also stage a whole wave
+constexpr int kOutboxSingle = 16;
+constexpr int kOutboxFull = 64;
 
-struct GradTable {
-  int* keys;    // [kTableCap], -1 = empty
-  float* vals;  // [16][kTableCap]
+template <int APP>
+struct TableShape {
+  static constexpr int cap = APP == 1 ? kTableCapFull : kTableCapSingle;
+  static constexpr int outbox = APP == 1 ? kOutboxFull : kOutboxSingle;
 };
 
-// all threads of the workgroup; needs a barrier before the table is used
-__device__ __forceinline__ void table_clear(const GradTable& t) {
-  for (int i = threadIdx.x; i < kTableCap; i += blockDim.x) {
-    t.keys[i] = -1;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) t.vals[c * kTableCap + i] = 0.0f;
-  }
+// The capacity is a compile-time constant: a run-time one made the adjoint
+// spill registers to scratch memory.
+template <int CAP>
+struct GradTable {
+  static constexpr int cap = CAP;
+  int* keys;    // [cap], -1 = empty
+  float* vals;  // [16][cap]
+};
+
+// home slot of a key: multiplicative hash scaled to [0, cap)
+template <int CAP>
+__device__ __forceinline__ int table_home(const GradTable<CAP>& t, int key) {
+  const unsigned h = (unsigned)key * 2654435761u;
+  return (int)(((unsigned long long)h * (unsigned)CAP) >> 32);
 }
 
-// C0: the first term that may be nonzero (texel-only records start at 4)
-template <int C0 = 0>
-__device__ __forceinline__ bool table_add(const GradTable& t, int key, const float* v) {
-  const unsigned h = ((unsigned)key * 2654435761u) >> (32 - kTableBits);
-  for (int p = 0; p < kTableProbes; ++p) {
-    const int slot = (int)((h + (unsigned)p) & (kTableCap - 1));
-    int k = __hip_atomic_load(&t.keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (k == -1) k = atomicCAS(&t.keys[slot], -1, key);
-    if (k == -1 || k == key) {
+// all threads of the workgroup; needs a barrier before the table is used
+template <int CAP>
+__device__ __forceinline__ void table_clear(const GradTable<CAP>& t) {
+  for (int i = threadIdx.x; i < t.cap; i += blockDim.x) {
+    t.keys[i] = -1;
 #pragma unroll
-      for (int c = C0; c < 16; ++c)
-        if (v[c] != 0.0f) atomicAdd(&t.vals[c * kTableCap + slot], v[c]);
-      return true;
-    }
+    for (int c = 0; c < 16; ++c) t.vals[c * t.cap + i] = 0.0f;
   }
-  return false;
 }
 
 // the record's table slot (claimed if new), or -1 when kTableProbes probes
-// find neither the key nor an empty slot
-__device__ __forceinline__ int table_slot(const GradTable& t, int key) {
-  const unsigned h = ((unsigned)key * 2654435761u) >> (32 - kTableBits);
+// (linear, wrapping) find neither the key nor an empty slot
+template <int CAP>
+__device__ __forceinline__ int table_slot(const GradTable<CAP>& t, int key) {
+  int slot = table_home(t, key);
   for (int p = 0; p < kTableProbes; ++p) {
-    const int slot = (int)((h + (unsigned)p) & (kTableCap - 1));
     int k = __hip_atomic_load(&t.keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (k == -1) k = atomicCAS(&t.keys[slot], -1, key);
     if (k == -1 || k == key) return slot;
+    slot = slot + 1 == t.cap ? 0 : slot + 1;
   }
   return -1;
+}
+
+// C0: the first term that may be nonzero (texel-only records start at 4)
+template <int C0, int CAP>
+__device__ __forceinline__ bool table_add(const GradTable<CAP>& t, int key, const float* v) {
+  const int slot = table_slot(t, key);
+  if (slot < 0) return false;
+#pragma unroll
+  for (int c = C0; c < 16; ++c)
+    if (v[c] != 0.0f) atomicAdd(&t.vals[c * t.cap + slot], v[c]);
+  return true;
 }
 
 // all threads of the workgroup, after a barrier: every entry to global
 // memory once (16 consecutive threads per entry, one term each), and the
 // table left empty (a barrier must follow)
-__device__ __forceinline__ void table_flush(const GradTable& t, const Grads& g, int RR, int R) {
-  for (int i = threadIdx.x; i < kTableCap * 16; i += blockDim.x) {
+template <int CAP>
+__device__ __forceinline__ void table_flush(const GradTable<CAP>& t, const Grads& g, int RR,
+                                            int R) {
+  for (int i = threadIdx.x; i < t.cap * 16; i += blockDim.x) {
     const int slot = i >> 4;
     const int c = i & 15;
     const int key = t.keys[slot];
     if (key < 0) continue;
-    const float x = t.vals[c * kTableCap + slot];
-    t.vals[c * kTableCap + slot] = 0.0f;
+    const float x = t.vals[c * t.cap + slot];
+    t.vals[c * t.cap + slot] = 0.0f;
     if (x != 0.0f) atomicAdd(record_addr(g, key, c, RR, R), x);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kTableCap; i += blockDim.x) t.keys[i] = -1;
+  for (int i = threadIdx.x; i < t.cap; i += blockDim.x) t.keys[i] = -1;
 }
 
 // Value of lane ^ M, exchanged without the LDS crossbar where gfx950 allows:
@@ -556,10 +604,11 @@ __device__ __forceinline__ void merge_level(int& key, float (&v)[16], int lane) 
 // registers: a win for the full appearance model, whose two records per step
 // already hold it at two waves per SIMD (3.58 -> 3.02 ms per frame), a loss
 // for the single map, which it would push from three waves to two.
-template <int LPR, int C0 = 0, bool SPREAD = false>
+template <int LPR, int C0, bool SPREAD, int CAP>
 __device__ __forceinline__ void emit_records(int key, float ds, float px, float py, float pz,
                                              const Taps& tp, float mr, float mg, float mb, int lane,
-                                             int RR, int R, const Grads& g, const GradTable* tab,
+                                             int RR, int R, const Grads& g,
+                                             const GradTable<CAP>* tab,
                                              const Outbox& ob) {
   float v[16];
   v[0] = ds;
@@ -597,14 +646,14 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
         const int c = lane & 15;
         if (r < n && c >= C0) {
           const float x = ob.vals[r * kStageStride + c];
-          if (x != 0.0f) atomicAdd(&tab->vals[c * kTableCap + ob.keys[r]], x);
+          if (x != 0.0f) atomicAdd(&tab->vals[c * tab->cap + ob.keys[r]], x);
         }
       }
       __builtin_amdgcn_wave_barrier();
     }
     outbox_send(ob, key >= 0 && slot < 0, key, v, lane, g, RR, R);
   } else {
-    const bool over = key >= 0 && !(tab && table_add<C0>(*tab, key, v));
+    const bool over = key >= 0 && !(tab && table_add<C0, CAP>(*tab, key, v));
     outbox_send(ob, over, key, v, lane, g, RR, R);
   }
 }
@@ -629,7 +678,8 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
 template <int LPR, int TEX, int APP>
 __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParams& w, const RayIn& r,
                                               const Upstream& u, bool has_ray, int sub, int lane,
-                                              const Grads& g, const GradTable* tab,
+                                              const Grads& g,
+                                              const GradTable<TableShape<APP>::cap>* tab,
                                               const Outbox& ob, Counters& cnt,
                                               bool dist_on = false) {
   const int R = s.res;
@@ -863,17 +913,17 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         cur = ex.next;
       }
     }
-    emit_records<LPR, 0, APP == 1>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane,
+    emit_records<LPR, 0, APP == 1, TableShape<APP>::cap>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane,
                                    RR, R, g, tab, ob);
     if constexpr (APP == 1)
-      emit_records<LPR, 4, true>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R,
+      emit_records<LPR, 4, true, TableShape<APP>::cap>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R,
                                  g, tab, ob);
   }
   // the last visited cell, and the unvisited cell behind an early-stopped ray's exit face
-  emit_records<LPR, 0, APP == 1>(lead && a_cell >= 0 ? (a_cell * MAPS) * RR + a_tp.base : -1,
+  emit_records<LPR, 0, APP == 1, TableShape<APP>::cap>(lead && a_cell >= 0 ? (a_cell * MAPS) * RR + a_tp.base : -1,
                                  a_ds, a_px, a_py, a_pz, a_tp, a_mr, a_mg, a_mb, lane, RR, R, g,
                                  tab, ob);
-  emit_records<LPR, 0, APP == 1>(lead && c_cell >= 0 ? (c_cell * MAPS) * RR + tp.base : -1, 0.0f,
+  emit_records<LPR, 0, APP == 1, TableShape<APP>::cap>(lead && c_cell >= 0 ? (c_cell * MAPS) * RR + tp.base : -1, 0.0f,
                                  c_px, c_py, c_pz, tp, 0.0f, 0.0f, 0.0f, lane, RR, R, g, tab, ob);
 }
 

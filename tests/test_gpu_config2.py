@@ -57,7 +57,7 @@ def c2():
     c.ds, perm, inv = voro.voro_morton_reorder(ds0)
     voro.voro_prepare(c.ds)
     c.perm, c.inv = perm.cpu().numpy(), inv.cpu().numpy()
-    c.params = autotune.params_for("shell100k", "fwd")
+    c.params = autotune.params_for(c.ds, [c.cam], "fwd")
     c.dev = dev
     return c
 

