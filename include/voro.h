@@ -376,6 +376,28 @@ voro_status voro_render_views_bwd(const voro_scene* scene, void* ws, size_t ws_b
                                   float* g_density, float* g_texels, uint64_t* stats,
                                   void* stream);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): voro_render_views_fwd
+ * with its scratch - the tile-queue counters, the camera centres and their
+ * cells, the nearest-site search's partial results - in a static device
+ * array of the library (about 65 KB per GPU, held until the process ends)
+ * instead of the workspace.  The workspace is only read: it must hold the
+ * records voro_prepare wrote (voro_workspace_size bytes always suffice).
+ * Outputs, arguments, validation and results are those of
+ * voro_render_views_fwd.  V above VORO_MAX_VIEWS (the scratch's maximum) is
+ * rejected with VORO_EINVAL.  Nothing is allocated: no hipMalloc, hipFree or
+ * allocating library routine is called (the first call on a device looks
+ * the array's device address up).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (different streams, or threads)
+ * race and must be serialised by the caller.
+ */
+voro_status voro_render_views_fwd_noalloc(const voro_scene* scene, const void* ws,
+                                          size_t ws_bytes, const voro_camera* cams, int32_t V,
+                                          const voro_params* params, float* rgb, float* T,
+                                          float* ray_rgbT, int32_t* nsteps, uint64_t* stats,
+                                          void* stream);
+
 /* ------------------------------------------------- scene preprocessing */
 
 /*

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "camera_impl.hpp"
 #include "host_common.hpp"
@@ -622,11 +623,88 @@ static voro_status views_common(bool backward, const voro_scene* scene, const vo
   return check_launch(backward ? "voro_render_views_bwd" : "voro_render_views_fwd");
 }
 
+// ------------------------------------------------- allocation-free launch
+//
+// voro_render_views_fwd_noalloc keeps the launch's scratch in a file-scope
+// device array instead of the caller's workspace.  Each GPU holds its own
+// copy until the process ends; host code never passes the array's name to a
+// kernel (on the host it only stands in for the symbol) but the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kViewsScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The current device's scratch address (looked up once per device).
+static voro_status static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(VORO_ENODEV, "no current HIP device");
+  }
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(VORO_EUNSUPPORTED, "device %d: the static scratch covers devices 0..%d", dev,
+                kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(VORO_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return VORO_OK;
+}
+
 }  // namespace voro
 
 using namespace voro;
 
 extern "C" {
+
+voro_status voro_render_views_fwd_noalloc(const voro_scene* scene, const void* ws,
+                                          size_t ws_bytes, const voro_camera* cams, int32_t V,
+                                          const voro_params* params, float* rgb, float* T,
+                                          float* ray_rgbT, int32_t* nsteps, uint64_t* stats,
+                                          void* stream) {
+  if (!rgb || !T) return fail(VORO_EINVAL, "rgb and T must not be NULL");
+  if (ray_rgbT && !aligned(ray_rgbT, 16)) return fail(VORO_EINVAL, "ray_rgbT must be 16-byte aligned");
+  if (V > VORO_MAX_VIEWS)
+    return fail(VORO_EINVAL, "V = %d views exceeds the static scratch's maximum of %d", V,
+                VORO_MAX_VIEWS);
+  int64_t nr = 0, np = 0;
+  voro_status st = check_cameras(cams, V, &nr, &np);
+  if (st != VORO_OK) return st;
+  for (int v = 0; v < V; ++v)
+    if (cams[v].spp > 1 && !ray_rgbT)
+      return fail(VORO_EINVAL, "ray_rgbT is required when a view has spp > 1");
+  if ((st = check_device()) != VORO_OK) return st;
+  void* base = nullptr;
+  if ((st = static_scratch(&base)) != VORO_OK) return st;
+  const ViewsScratch sc{(char*)base, (char*)base + kViewsScratchPartials};
+  ViewsArgs a = {};
+  a.rgb = rgb;
+  a.T = T;
+  a.ray_rgbT = ray_rgbT;
+  a.nsteps = nsteps;
+  a.stats = reinterpret_cast<unsigned long long*>(stats);
+  bool any_spp = false;
+  st = views_common(false, scene, ws, ws_bytes, &sc, cams, V, params, a, &nr, &np, &any_spp,
+                    stream);
+  if (st != VORO_OK) return st;
+  if (any_spp) {
+    const int n = (int)np;
+    hipLaunchKernelGGL(k_views_resolve, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       a.ct, reinterpret_cast<const float4*>(ray_rgbT), rgb, T, n);
+    st = check_launch("voro_render_views_fwd_noalloc: resolve");
+  }
+  return st;
+}
 
 voro_status voro_gen_rays(const voro_camera* cams, int32_t V, float* o, float* d, float* tmax,
                           void* stream) {

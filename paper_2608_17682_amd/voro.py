@@ -40,6 +40,7 @@ EXPORTS = [
     "voro_version", "voro_last_error", "voro_default_params", "voro_workspace_size",
     "voro_prepare", "voro_locate_origins", "voro_render_fwd", "voro_render_bwd",
     "voro_camera_counts", "voro_gen_rays", "voro_render_views_fwd", "voro_render_views_bwd",
+    "voro_render_views_fwd_noalloc",
     "voro_reorder_scratch_size", "voro_morton_reorder", "voro_cast_texels",
 ]
 
@@ -111,6 +112,9 @@ def lib():
             "voro_render_views_bwd": ([P(voro_scene), vp, ctypes.c_size_t, P(voro_camera), i32,
                                        P(voro_params), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
                                       i32),
+            "voro_render_views_fwd_noalloc": ([P(voro_scene), vp, ctypes.c_size_t,
+                                               P(voro_camera), i32, P(voro_params), vp, vp, vp,
+                                               vp, vp, vp], i32),
             "voro_reorder_scratch_size": ([i32, i64, P(ctypes.c_size_t)], i32),
             "voro_morton_reorder": ([P(voro_scene), P(voro_scene), vp, vp, vp, ctypes.c_size_t,
                                      vp], i32),
@@ -396,6 +400,20 @@ def voro_render_views_fwd(ds: DeviceScene, cams, params=None, rgb=None, T=None, 
                                        ctypes.byref(p), _ptr(rgb), _ptr(T), _ptr(ray_rgbT),
                                        _ptr(nsteps), _ptr(stats), _stream(stream)),
            "voro_render_views_fwd")
+    return rgb, T, ray_rgbT
+
+
+def voro_render_views_fwd_noalloc(ds: DeviceScene, cams, params, rgb, T, ray_rgbT=None,
+                                  nsteps=None, stats=None, stream=None):
+    """voro_render_views_fwd with the library's static scratch: every output is
+    caller-provided and nothing is allocated (the prepared workspace is read)."""
+    arr = camera_array(cams)
+    sc = ds.c()
+    _check(lib().voro_render_views_fwd_noalloc(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, arr,
+                                               len(arr), ctypes.byref(params), _ptr(rgb), _ptr(T),
+                                               _ptr(ray_rgbT), _ptr(nsteps), _ptr(stats),
+                                               _stream(stream)),
+           "voro_render_views_fwd_noalloc")
     return rgb, T, ray_rgbT
 
 
