@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "voro.h"
 #include "voro_device.hpp"
 
@@ -20,6 +22,7 @@ struct CamTable {
   int g[VORO_MAX_VIEWS];             // thin lens: samples per pixel side (spp = g*g)
   int gx[VORO_MAX_VIEWS];            // a pixel's samples laid out as a gx x gy block
   int gy[VORO_MAX_VIEWS];            // of the view's sample grid (spp = gx*gy)
+  float focal[VORO_MAX_VIEWS];       // focal length in pixels (camera_focal)
   int V;
 };
 
@@ -47,11 +50,22 @@ __device__ __forceinline__ void concentric(float a, float b, float& x, float& y)
   y = r * sn;
 }
 
-// Ray of pixel (px, py), sample s of camera c.  Returns false (tmax = 0)
-// for fisheye pixels outside the image circle.
-__device__ __forceinline__ bool gen_ray(const voro_camera& c, int g, int px, int py, int s,
-                                        float& ox, float& oy, float& oz, float& dx, float& dy,
-                                        float& dz, float& tmax) {
+// Focal length in pixels, once per view on the host: (W/2) / (fov/2) for
+// the equidistant fisheye (theta = r / f), (W/2) / tan(fov/2) otherwise
+// (evaluated in FP64 and rounded once).  Kept out of the kernels so that no
+// per-ray tangent (and its constants) competes for registers with the walk.
+static inline float camera_focal(const voro_camera& c) {
+  const float W = (float)c.width;
+  if (c.model == VORO_CAM_FISHEYE) return (0.5f * W) / (0.5f * c.fov);
+  return (float)((0.5 * (double)W) / std::tan(0.5 * (double)c.fov));
+}
+
+// Ray of pixel (px, py), sample s of camera c with focal length f (pixels,
+// camera_focal).  Returns false (tmax = 0) for fisheye pixels outside the
+// image circle.
+__device__ __forceinline__ bool gen_ray(const voro_camera& c, int g, float f, int px, int py,
+                                        int s, float& ox, float& oy, float& oz, float& dx,
+                                        float& dy, float& dz, float& tmax) {
   const float* M = c.c2w;
   const float W = (float)c.width;
   const float H = (float)c.height;
@@ -63,7 +77,6 @@ __device__ __forceinline__ bool gen_ray(const voro_camera& c, int g, int px, int
   float cx, cy, cz;
   bool valid = true;
   if (c.model == VORO_CAM_FISHEYE) {
-    const float f = (0.5f * W) / (0.5f * c.fov);
     const float r2 = u * u + v * v;  // exact on the half-integer pixel grid
     valid = r2 <= 0.25f * W * W;
     const float r = sqrtf(r2);
@@ -79,7 +92,6 @@ __device__ __forceinline__ bool gen_ray(const voro_camera& c, int g, int px, int
     }
     cz = ct;
   } else {
-    const float f = (0.5f * W) / tanf(0.5f * c.fov);
     const float x = u / f;
     const float y = v / f;
     if (c.model == VORO_CAM_THIN_LENS) {

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(256) k_gen_rays(CamTable ct, float* __restrict
   const int px = pix % c.width;
   const int py = pix / c.width;
   float ox, oy, oz, dx, dy, dz, tm;
-  gen_ray(c, ct.g[v], px, py, s, ox, oy, oz, dx, dy, dz, tm);
+  gen_ray(c, ct.g[v], ct.focal[v], px, py, s, ox, oy, oz, dx, dy, dz, tm);
   o[3 * (size_t)i] = ox;
   o[3 * (size_t)i + 1] = oy;
   o[3 * (size_t)i + 2] = oz;
@@ -149,7 +149,8 @@ __device__ __forceinline__ bool tile_ray(const CamTable& ct, int unit, int sx, i
 __device__ __forceinline__ RayIn views_ray(const ViewsArgs& a, const TileRay& tr, bool* capped) {
   const voro_camera& c = a.ct.cam[tr.view];
   RayIn r;
-  gen_ray(c, a.ct.g[tr.view], tr.px, tr.py, tr.s, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, r.tmax);
+  gen_ray(c, a.ct.g[tr.view], a.ct.focal[tr.view], tr.px, tr.py, tr.s, r.ox, r.oy, r.oz, r.dx,
+          r.dy, r.dz, r.tmax);
   r.start = a.center_cell[tr.view];
   const bool moved = c.model == VORO_CAM_ROLLING_SHUTTER || c.model == VORO_CAM_MOTION_BLUR ||
                      (c.model == VORO_CAM_THIN_LENS && c.lens_radius > 0.0f);
@@ -180,17 +181,30 @@ __device__ __forceinline__ void write_ray_out(const ViewsArgs& a, const TileRay&
 // wave of the grid takes one tile (workgroups renumbered per XCD) and the
 // hardware dispatcher balances the load.  One lane per ray walks with staged
 // edge rows (dynamic LDS: kStageBytesPerWave per wave) unless the edges are
-// ranked in half precision.
+// ranked in half precision.  The persistent one-lane-per-ray exact walk is
+// held to 96 VGPRs, five waves per SIMD instead of four: its few spills sit
+// outside the walk loop, and the extra wave hides more of the gathers'
+// latency.
+template <int LPR, int APP, bool PERSIST, bool E16>
+struct FwdWaves {
+  static constexpr int value = (PERSIST && LPR == 1 && APP == 0 && !E16) ? 5 : 1;
+};
+
 template <int LPR, int TEX, int APP, bool PERSIST, bool E16>
-__global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(FwdWaves<LPR, APP, PERSIST, E16>::value, 8)))
+    k_views_fwd(ViewsArgs a) {
   extern __shared__ float4 slabs[];
+  __shared__ unsigned long long s_stats[kWgStats];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int grp = lane / LPR;
   const int sub = lane % LPR;
   const int xcd = blockIdx.x % kXcd;
-  Counters cnt;
-  uint32_t capped_n = 0;
+  if constexpr (PERSIST) {
+    wg_stats_clear(s_stats);
+    __syncthreads();
+  }
   int probe = 0;
   int tile = PERSIST ? -1 : xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
   for (;;) {
@@ -200,35 +214,36 @@ __global__ void __launch_bounds__(256) k_views_fwd(ViewsArgs a) {
     } else if (tile >= a.total_tiles) {
       break;
     }
+    Counters cnt;
+    bool capped = false;
     TileRay tr;
+    const bool has = tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr);
     if constexpr (LPR == 1 && !E16) {
-      const bool has = tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr);
       RayIn r{};
-      if (has) {
-        bool capped = false;
-        r = views_ray(a, tr, &capped);
-        capped_n += capped ? 1u : 0u;
-      }
+      if (has) r = views_ray(a, tr, &capped);
       const RayOut out = walk_forward_staged<TEX, APP>(
           a.s, a.w, r, has, lane, slabs + wave * (kStageBytesPerWave / 16), nullptr, 0, cnt);
       if (has) write_ray_out<LPR>(a, tr, out);
-    } else {
-      if (!tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr)) {
-        if constexpr (!PERSIST) break;
-        continue;
-      }
-      bool capped = false;
+    } else if (has) {
       const RayIn r = views_ray(a, tr, &capped);
-      capped_n += capped ? 1u : 0u;
       const RayOut out = walk_forward<LPR, TEX, APP, E16>(a.s, a.w, r, sub, nullptr, 0, cnt);
       if (sub == 0) write_ray_out<LPR>(a, tr, out);
     }
+    if (a.stats) {
+      const bool mine = has && sub == 0;
+      if constexpr (PERSIST) {
+        tile_counters_to_lds(cnt, mine, capped, lane, s_stats);
+      } else {
+        flush_counters(cnt, mine, lane, a.stats);
+        const uint32_t cp = wave_sum_u32(mine && capped ? 1u : 0u);
+        if (lane == 0 && cp) atomicAdd(&a.stats[VORO_STAT_LOCATE_CAP], (unsigned long long)cp);
+      }
+    }
     if constexpr (!PERSIST) break;
   }
-  if (a.stats) {
-    flush_counters(cnt, sub == 0, lane, a.stats);
-    const uint32_t cp = wave_sum_u32(sub == 0 ? capped_n : 0u);
-    if (lane == 0 && cp) atomicAdd(&a.stats[VORO_STAT_LOCATE_CAP], (unsigned long long)cp);
+  if constexpr (PERSIST) {
+    __syncthreads();
+    if (a.stats) wg_stats_flush(s_stats, a.stats);
   }
 }
 
@@ -406,6 +421,7 @@ static CamTable make_table(const voro_camera* cams, int V, int tile_w, int tile_
     // thin-lens samples tile the pixel as g x g; time samples as a row
     ct.gx[v] = cams[v].model == VORO_CAM_THIN_LENS ? g : cams[v].spp;
     ct.gy[v] = cams[v].model == VORO_CAM_THIN_LENS ? g : 1;
+    ct.focal[v] = camera_focal(cams[v]);
     ct.ray_off[v] = ro;
     ct.pix_off[v] = po;
     ct.tile_off[v] = to;

@@ -298,7 +298,12 @@ __device__ __forceinline__ Exit decide_exit(const Best& r, const float4* __restr
       const float u = 0.5f * cross_u(E, q2x, q2y, q2z, dx, dy, dz);
       if (u - r.t1 <= win) {
         const int j = __float_as_int(E.w);
-        const double t = cross64(cells, i, j, ox, oy, oz, dx, dy, dz);
+        // The empty asm makes the ray's coordinates look redefined here, so
+        // their FP64 conversions stay in this rarely taken branch; hoisted
+        // out of the walk they would hold 12 VGPRs for the whole walk.
+        float o0 = ox, o1 = oy, o2 = oz, d0 = dx, d1 = dy, d2 = dz;
+        asm volatile("" : "+v"(o0), "+v"(o1), "+v"(o2), "+v"(d0), "+v"(d1), "+v"(d2));
+        const double t = cross64(cells, i, j, o0, o1, o2, d0, d1, d2);
         if (t < tb || (t == tb && t < __builtin_huge_val() && j < jb)) {
           tb = t;
           jb = j;

@@ -78,6 +78,52 @@ __device__ __forceinline__ void flush_counters(Counters c, bool contribute, int 
   }
 }
 
+// Per-workgroup stats in LDS (index = VORO_STAT_*) for the persistent
+// kernels, whose waves walk one ray per lane group per tile: after each tile
+// the lanes add their counters there (per-ray events as one ballot count per
+// wave, per-step sums as LDS atomics), so no counter and no cross-lane
+// shuffle address stays live across the tile loop.
+constexpr int kWgStats = 10;
+
+__device__ __forceinline__ void wg_stats_clear(unsigned long long* s) {
+  if (threadIdx.x < kWgStats) s[threadIdx.x] = 0ull;
+}
+
+// Every lane of the wave must call this; a lane's counters cover at most one
+// ray since they were zeroed.
+__device__ __forceinline__ void tile_counters_to_lds(const Counters& c, bool contribute,
+                                                     bool capped, int lane,
+                                                     unsigned long long* s) {
+  const unsigned n_rays = __popcll(__ballot(contribute && c.rays != 0u));
+  const unsigned n_bad = __popcll(__ballot(contribute && c.bad != 0u));
+  const unsigned n_max = __popcll(__ballot(contribute && c.maxsteps != 0u));
+  const unsigned n_nan = __popcll(__ballot(contribute && c.nan != 0u));
+  const unsigned n_cap = __popcll(__ballot(contribute && capped));
+  if (contribute) {
+    if (c.steps) atomicAdd(&s[VORO_STAT_STEPS], (unsigned long long)c.steps);
+    if (c.deg) atomicAdd(&s[VORO_STAT_DEGREE_SUM], (unsigned long long)c.deg);
+    if (c.redecide) atomicAdd(&s[VORO_STAT_FP64_REDECIDE], (unsigned long long)c.redecide);
+    if (c.skipped) atomicAdd(&s[VORO_STAT_SKIPPED], (unsigned long long)c.skipped);
+  }
+  if (lane == 0) {
+    if (n_rays) atomicAdd(&s[VORO_STAT_RAYS], (unsigned long long)n_rays);
+    if (n_bad) atomicAdd(&s[VORO_STAT_BAD_START], (unsigned long long)n_bad);
+    if (n_max) atomicAdd(&s[VORO_STAT_MAX_STEPS], (unsigned long long)n_max);
+    if (n_nan) atomicAdd(&s[VORO_STAT_NAN], (unsigned long long)n_nan);
+    if (n_cap) atomicAdd(&s[VORO_STAT_LOCATE_CAP], (unsigned long long)n_cap);
+  }
+}
+
+// after a barrier that follows every wave's last tile.  The thread index is
+// read afresh (empty asm) so that the slot address is not kept live, or
+// spilled, from the kernel's start.
+__device__ __forceinline__ void wg_stats_flush(const unsigned long long* s,
+                                               unsigned long long* stats) {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  if (t < kWgStats && s[t]) atomicAdd(&stats[t], s[t]);
+}
+
 // One step of the walk: the exit of cell `cur` entered at t_in.  lrow: the
 // cell's edge row staged in LDS by the wave (one lane per ray), or null to
 // gather it from global memory.  E16: rank the row from its half-precision
