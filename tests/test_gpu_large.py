@@ -241,7 +241,8 @@ def test_config5_persistent_views_adjoint_equals_explicit(dev, c5):
     p = c5.pb
     npx = int(c5.off[-1])
     g_rgb = synth.upstream(npx, 5, with_gT=False)[0]
-    rgb, T, ray_rgbT = voro.voro_render_views_fwd(c5.ds, c5.cams, c5.pf)
+    st_v = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    rgb, T, ray_rgbT = voro.voro_render_views_fwd(c5.ds, c5.cams, c5.pf, stats=st_v)
     gv = voro.voro_render_views_bwd(c5.ds, c5.cams, rgb, T, ray_rgbT, to_dev(g_rgb, dev), None, p)
     O, D, TM = voro.voro_gen_rays(c5.cams, dev)
     centres = to_dev(np.array([cam.c2w[:, 3] for cam in c5.cams], np.float32), dev)
@@ -249,9 +250,14 @@ def test_config5_persistent_views_adjoint_equals_explicit(dev, c5):
     nr = [cam.n_rays for cam in c5.cams]
     hint = torch.cat([cc[i:i + 1].expand(k) for i, k in enumerate(nr)]).contiguous()
     S = voro.voro_locate_origins(c5.ds, O, hint=hint)
-    rgb_e, T_e = voro.voro_render_fwd(c5.ds, O, D, TM, S, voro.default_params())
-    # the multi-view launch's per-ray results are the explicit path's, bit for bit
+    st_e = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    rgb_e, T_e = voro.voro_render_fwd(c5.ds, O, D, TM, S, voro.default_params(), stats=st_e)
+    # the multi-view launch's per-ray results are the explicit path's, bit for
+    # bit, and so are the walk statistics its workgroups gather
     assert torch.equal(rgb_e, ray_rgbT[:, :3].contiguous()) and torch.equal(T_e, ray_rgbT[:, 3])
+    keep = [voro.STAT_NAMES.index(k) for k in ("rays", "steps", "degree_sum", "max_steps", "nan",
+                                                "bad_start", "fp64_redecide", "skipped")]
+    assert st_v[keep].tolist() == st_e[keep].tolist()
     gr = []
     off = 0
     for cam in c5.cams:

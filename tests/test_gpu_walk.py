@@ -255,24 +255,37 @@ def test_autograd_function(dev, c1):
     assert_grad_close(tex.grad.cpu().numpy(), gt, "texels")
 
 
-@pytest.mark.parametrize("lpr,schedule", [(2, voro.SCHEDULE_GRID), (1, voro.SCHEDULE_REFILL),
-                                          (1, voro.SCHEDULE_PERSISTENT)])
+WALK_STATS = ("rays", "steps", "degree_sum", "max_steps", "nan", "bad_start", "fp64_redecide",
+              "skipped")
+
+
+@pytest.mark.parametrize("lpr,schedule", [(2, voro.SCHEDULE_GRID), (1, voro.SCHEDULE_GRID),
+                                          (1, voro.SCHEDULE_REFILL), (1, voro.SCHEDULE_PERSISTENT),
+                                          (2, voro.SCHEDULE_PERSISTENT)])
 def test_views_fwd_equals_explicit_rays(dev, c1, lpr, schedule):
     # every multi-view schedule generates the same rays, starts in the same
-    # cells and takes the same walk as gen_rays + locate + render_fwd
+    # cells and takes the same walk as gen_rays + locate + render_fwd, and
+    # counts the same walk statistics (however each kernel gathers them)
     cams = synth.config5_cameras(scale=0.06) + synth.motion_blur_cameras(scale=0.05)
     for cm in cams:
         cm.tmax = 4.0
     announce(f"views fwd vs explicit, mixed cameras, lpr {lpr} schedule {schedule}")
     p = voro.default_params(lanes_per_ray=lpr, schedule=schedule)
-    rgb_v, T_v, ray_v = voro.voro_render_views_fwd(c1.ds, cams, p)
+    st_v = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    rgb_v, T_v, ray_v = voro.voro_render_views_fwd(c1.ds, cams, p, stats=st_v)
     O, D, TM = voro.voro_gen_rays(cams, dev)
     centres = to_dev(f32([cm.c2w[:, 3] for cm in cams]), dev)
     cc = voro.voro_locate_origins(c1.ds, centres)
     nr = [cm.n_rays for cm in cams]
     hint = torch.cat([cc[i:i + 1].expand(n) for i, n in enumerate(nr)]).contiguous()
     S = voro.voro_locate_origins(c1.ds, O, hint=hint)
-    rgb_e, T_e = voro.voro_render_fwd(c1.ds, O, D, TM, S, voro.default_params(lanes_per_ray=1))
+    st_e = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    rgb_e, T_e = voro.voro_render_fwd(c1.ds, O, D, TM, S, voro.default_params(lanes_per_ray=1),
+                                      stats=st_e)
+    sv = dict(zip(voro.STAT_NAMES, st_v.cpu().tolist()))
+    se = dict(zip(voro.STAT_NAMES, st_e.cpu().tolist()))
+    assert sv["rays"] == int((TM > 0).sum().item()) and sv["steps"] > sv["rays"]
+    assert {k: sv[k] for k in WALK_STATS} == {k: se[k] for k in WALK_STATS}
     rgb_e, T_e = rgb_e.cpu().numpy(), T_e.cpu().numpy()
     ray_v = ray_v.cpu().numpy()
     rgb_v, T_v = rgb_v.cpu().numpy(), T_v.cpu().numpy()
