@@ -115,7 +115,7 @@ def stats_dict(t):
 # ----------------------------------------------------------- oracle legs
 # Both run before this process touches the GPU: the oracle's pool forks.
 
-def oracle_config5_sample(scene, workers, px_per_view=2):
+def oracle_config5_sample(scene, workers, px_per_view=4):
     """FP64 oracle forward + adjoint on a few pixels of each of the 8 views."""
     from oracle import batch, cameras
     from paper_2608_17682_amd import synth
