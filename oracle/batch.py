@@ -105,14 +105,16 @@ class _Sparse1:
 
 
 class _SparseTex:
-    """Indexable like g_texels[i, r, c, :3] for the accumulation in grad_ray."""
+    """Indexable like g_texels[i, ...] for the accumulation in grad_ray; each
+    touched cell holds a dense block shaped like one cell's texels ([R,R,4],
+    or [2,R,R,4] for the two maps of the full appearance model)."""
 
-    def __init__(self, res):
-        self.res = res
+    def __init__(self, cell_shape):
+        self.cell_shape = tuple(cell_shape)
         self.d = {}
 
     def _cell(self, i):
-        return self.d.setdefault(int(i), np.zeros((self.res, self.res, 4)))
+        return self.d.setdefault(int(i), np.zeros(self.cell_shape))
 
     def __getitem__(self, key):
         return self._cell(key[0])[key[1:]]
@@ -124,15 +126,16 @@ class _SparseTex:
 def sparse_gradients(sites, density, texels, o, d, tmax, records, g_rgb, g_T=None):
     """FP64 gradients of L = sum_r g_rgb[r].rgb[r] + g_T[r] T[r] over the rays
     whose record is given (records[r] None = ray left out), restricted to the
-    cells they touch.  Single-map appearance (texels [N,R,R,4]).
+    cells they touch.  Texels [N,R,R,4] (single map) or [N,2,R,R,4] (the full
+    appearance model; the records say which model rendered them).
 
-    Returns (cells [C] sorted, g_sites [C,3], g_density [C], g_texels [C,R,R,4]);
-    every cell not listed has zero gradient.
+    Returns (cells [C] sorted, g_sites [C,3], g_density [C], g_texels [C, ...]
+    with one cell's texel shape); every cell not listed has zero gradient.
     """
     sites = walk.as64(sites)
     density = walk.as64(density)
-    res = texels.shape[1]
-    gs, gd, gt = _Sparse3(), _Sparse1(), _SparseTex(res)
+    cell_shape = tuple(np.shape(texels)[1:])
+    gs, gd, gt = _Sparse3(), _Sparse1(), _SparseTex(cell_shape)
     R = len(records)
     tm = np.broadcast_to(np.asarray(tmax, np.float64), (R,))
     for r, rec in enumerate(records):
@@ -144,5 +147,5 @@ def sparse_gradients(sites, density, texels, o, d, tmax, records, g_rgb, g_T=Non
     return (ids,
             np.array([gs.d.get(int(i), np.zeros(3)) for i in ids]).reshape(-1, 3),
             np.array([gd.d.get(int(i), 0.0) for i in ids]),
-            np.array([gt.d.get(int(i), np.zeros((res, res, 4))) for i in ids]).reshape(
-                -1, res, res, 4))
+            np.array([gt.d.get(int(i), np.zeros(cell_shape)) for i in ids]).reshape(
+                (-1,) + cell_shape))

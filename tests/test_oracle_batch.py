@@ -51,3 +51,35 @@ def test_sparse_gradients_equal_dense():
     np.testing.assert_allclose(gs, ws[ids], rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(gd, wd[ids], rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(gt, wt[ids], rtol=1e-12, atol=1e-15)
+
+
+def test_sparse_gradients_equal_dense_full_model():
+    # the two-map texel blocks of the full appearance model accumulate like
+    # the dense adjoint's [N, 2, R, R, 4] gradient
+    scene, o, d, tm = _rays()
+    tex = synth.full_texels(scene.n, scene.tex_res, seed=3)
+    rgb, T, recs = render.render_rays(scene.sites, scene.density, tex, o, d, tm, appearance=1)
+    res = batch.evaluate(scene.sites, scene.density, tex, o, d, tm, workers=2, chunk=11,
+                         keep_records=np.ones(len(o), bool), appearance=1)
+    assert np.array_equal(res["rgb"], rgb) and np.array_equal(res["T"], T)
+    g_rgb, _ = synth.upstream(len(o), 2)
+    ids, gs, gd, gt = batch.sparse_gradients(scene.sites, scene.density, tex, o, d, tm,
+                                             res["records"], g_rgb)
+    assert gt.shape[1:] == tex.shape[1:]
+    ws, wd, wt = adjoint.grad_rays(scene.sites, scene.density, tex, o, d, tm, recs, g_rgb,
+                                   np.zeros(len(o)))
+    touched = np.nonzero(np.any(ws != 0, 1) | (wd != 0) | np.any(wt != 0, (1, 2, 3, 4)))[0]
+    assert set(touched.tolist()) <= set(ids.tolist())
+    assert np.abs(wt[:, 1]).max() > 0    # the view map is exercised
+    np.testing.assert_allclose(gs, ws[ids], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(gd, wd[ids], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(gt, wt[ids], rtol=1e-12, atol=1e-15)
+
+
+def test_evaluate_equals_render_rays_sh():
+    scene, o, d, tm = _rays()
+    k = synth.sh_coeffs(scene.n, seed=3)
+    rgb, T, _ = render.render_rays(scene.sites, scene.density, k, o, d, tm, appearance=2)
+    res = batch.evaluate(scene.sites, scene.density, k, o, d, tm, workers=2, chunk=13,
+                         appearance=2)
+    assert np.array_equal(res["rgb"], rgb) and np.array_equal(res["T"], T)
