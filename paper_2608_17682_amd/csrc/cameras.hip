@@ -308,9 +308,21 @@ __global__ void __launch_bounds__(256) k_views_fwd_refill(ViewsArgs a) {
 
 // Backward work unit: a workgroup tile (the waves' tiles side by side, 2
 // wide), walked by the whole workgroup into one LDS gradient table that is
-// flushed to global memory before the next unit.
+// flushed to global memory before the next unit.  The persistent
+// one-lane-per-ray single-map adjoint is held to 128 VGPRs and a 528-entry
+// table, four workgroups of four waves per CU instead of three (its few
+// spills sit outside the walk loop); the other forms keep the larger table.
+template <int LPR, int APP, bool PERSIST>
+struct BwdShape {
+  static constexpr bool quad = PERSIST && LPR == 1 && APP == 0;
+  static constexpr int waves = quad ? 4 : 1;
+  static constexpr int cap = quad ? kTableCapQuad : TableShape<APP>::cap;
+};
+
 template <int LPR, int TEX, int APP, bool PERSIST>
-__global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(BwdShape<LPR, APP, PERSIST>::waves, 8)))
+    k_views_bwd(ViewsArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
@@ -321,7 +333,7 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   const int unit_w = a.tile_w * wx;
   const int unit_h = a.tile_h * (nwaves / wx);
   const int RR = a.s.res * a.s.res;
-  constexpr int kCap = TableShape<APP>::cap;
+  constexpr int kCap = BwdShape<LPR, APP, PERSIST>::cap;
   constexpr int kOb = TableShape<APP>::outbox;
   __shared__ int s_keys[kCap];
   __shared__ float s_vals[16 * kCap];
@@ -332,8 +344,9 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
   tab.keys = s_keys;
   tab.vals = s_vals;
   const Outbox ob{s_okeys[wave], s_ovals[wave], kOb};
+  __shared__ unsigned long long s_stats[kWgStats];
   table_clear(tab);
-  Counters cnt;
+  if constexpr (PERSIST) wg_stats_clear(s_stats);
   int probe = 0;
   int unit = PERSIST ? -1 : xcd_block(blockIdx.x, gridDim.x);
   for (;;) {
@@ -374,14 +387,26 @@ __global__ void __launch_bounds__(256) k_views_bwd(ViewsArgs a) {
       u.gb = a.g_rgb[3 * p + 2] * share;
       u.gT = a.g_T ? a.g_T[p] * share : 0.0f;
     }
-    // the whole wave walks its tile together (gradient records merge across lanes)
-    walk_backward<LPR, TEX, APP>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, ob, cnt);
+    // the whole wave walks its tile together (gradient records merge across
+    // lanes); its counters go to the workgroup's LDS stats after each unit
+    Counters cnt;
+    walk_backward<LPR, TEX, APP, kCap>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, ob, cnt);
+    if (a.stats) {
+      if constexpr (PERSIST) {
+        tile_counters_to_lds(cnt, has && sub == 0, false, lane, s_stats);
+      } else {
+        flush_counters(cnt, has && sub == 0, lane, a.stats);
+      }
+    }
     __syncthreads();
     table_flush(tab, a.g, RR, a.s.res);
     __syncthreads();
     if constexpr (!PERSIST) break;
   }
-  if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
+  if constexpr (PERSIST) {
+    __syncthreads();
+    if (a.stats) wg_stats_flush(s_stats, a.stats);
+  }
 }
 
 // pixel = mean of its samples, in sample order

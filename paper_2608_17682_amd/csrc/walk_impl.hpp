@@ -513,6 +513,9 @@ __device__ __forceinline__ void outbox_send(const Outbox& ob, bool send, int key
 // probes, measured slower; so did a smaller table with four workgroups).
 constexpr int kTableProbes = 8;
 constexpr int kTableCapSingle = 704;  // one texture map: 16-record outboxes beside it
+// the persistent one-lane-per-ray single-map adjoint runs four workgroups of
+// four waves per CU: 528 entries is the most that leaves LDS for four
+constexpr int kTableCapQuad = 528;
 constexpr int kTableCapFull = 512;    // two maps: the outboxes also stage a whole wave
 constexpr int kOutboxSingle = 16;
 constexpr int kOutboxFull = 64;
@@ -628,17 +631,15 @@ __device__ __forceinline__ void merge_level(int& key, float (&v)[16], int lane) 
   const int pk = xor_lane<M>(key, lane);
   const bool match = key >= 0 && pk == key;
   if (!__any(match)) return;
-  float pv[16];
+  // each partner term is added as it arrives (two registers in flight, not
+  // sixteen)
+  const bool add = match && (lane & M) == 0;
 #pragma unroll
-  for (int i = C0; i < 16; ++i) pv[i] = __int_as_float(xor_lane<M>(__float_as_int(v[i]), lane));
-  if (match) {
-    if ((lane & M) == 0) {
-#pragma unroll
-      for (int i = C0; i < 16; ++i) v[i] += pv[i];
-    } else {
-      key = -1;
-    }
+  for (int i = C0; i < 16; ++i) {
+    const float p = __int_as_float(xor_lane<M>(__float_as_int(v[i]), lane));
+    v[i] = add ? v[i] + p : v[i];
   }
+  if (match && (lane & M) != 0) key = -1;
 }
 
 // Merge equal-key records of butterfly partners across the wave (lane ^ m
@@ -724,11 +725,10 @@ __device__ __forceinline__ void emit_records(int key, float ds, float px, float 
 // and sum_j G_j w_j = 2 L_dist, so the suffix follows from the saved loss;
 // the interval ends move with their crossings through
 // dL_dist/dt = (dL/dsbar / 2 -+ dL/dds) s'(t), s'(t) = 1/(1+t)^2.
-template <int LPR, int TEX, int APP>
+template <int LPR, int TEX, int APP, int CAP = TableShape<APP>::cap>
 __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParams& w, const RayIn& r,
                                               const Upstream& u, bool has_ray, int sub, int lane,
-                                              const Grads& g,
-                                              const GradTable<TableShape<APP>::cap>* tab,
+                                              const Grads& g, const GradTable<CAP>* tab,
                                               const Outbox& ob, Counters& cnt,
                                               bool dist_on = false) {
   const int R = s.res;
@@ -962,17 +962,17 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         cur = ex.next;
       }
     }
-    emit_records<LPR, 0, APP == 1, TableShape<APP>::cap>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane,
+    emit_records<LPR, 0, APP == 1, CAP>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane,
                                    RR, R, g, tab, ob);
     if constexpr (APP == 1)
-      emit_records<LPR, 4, true, TableShape<APP>::cap>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R,
+      emit_records<LPR, 4, true, CAP>(v_key, 0.0f, 0.0f, 0.0f, 0.0f, tp, v_mr, v_mg, v_mb, lane, RR, R,
                                  g, tab, ob);
   }
   // the last visited cell, and the unvisited cell behind an early-stopped ray's exit face
-  emit_records<LPR, 0, APP == 1, TableShape<APP>::cap>(lead && a_cell >= 0 ? (a_cell * MAPS) * RR + a_tp.base : -1,
+  emit_records<LPR, 0, APP == 1, CAP>(lead && a_cell >= 0 ? (a_cell * MAPS) * RR + a_tp.base : -1,
                                  a_ds, a_px, a_py, a_pz, a_tp, a_mr, a_mg, a_mb, lane, RR, R, g,
                                  tab, ob);
-  emit_records<LPR, 0, APP == 1, TableShape<APP>::cap>(lead && c_cell >= 0 ? (c_cell * MAPS) * RR + tp.base : -1, 0.0f,
+  emit_records<LPR, 0, APP == 1, CAP>(lead && c_cell >= 0 ? (c_cell * MAPS) * RR + tp.base : -1, 0.0f,
                                  c_px, c_py, c_pz, tp, 0.0f, 0.0f, 0.0f, lane, RR, R, g, tab, ob);
 }
 
