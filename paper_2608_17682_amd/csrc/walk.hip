@@ -196,8 +196,20 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
 }
 
+// The one-lane-per-ray single-map form runs at four waves per SIMD with the
+// 528-entry table (as the persistent multi-view adjoint); the others keep
+// the larger table at three.
+template <int LPR, int APP>
+struct RenderBwdShape {
+  static constexpr bool quad = LPR == 1 && APP == 0;
+  static constexpr int waves = quad ? 4 : 1;
+  static constexpr int cap = quad ? kTableCapQuad : TableShape<APP>::cap;
+};
+
 template <int LPR, int TEX, int APP>
-__global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(RenderBwdShape<LPR, APP>::waves, 8)))
+    k_render_bwd(RayArgs a) {
   const int nwaves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -232,7 +244,7 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
       u.gD = a.g_dist[ray];
     }
   }
-  constexpr int kCap = TableShape<APP>::cap;
+  constexpr int kCap = RenderBwdShape<LPR, APP>::cap;
   constexpr int kOb = TableShape<APP>::outbox;
   __shared__ int s_keys[kCap];
   __shared__ float s_vals[16 * kCap];
@@ -246,7 +258,7 @@ __global__ void __launch_bounds__(256) k_render_bwd(RayArgs a) {
   __syncthreads();
   // all lanes take part: the gradient records are merged across the wave,
   // then across the workgroup in the LDS table
-  walk_backward<LPR, TEX, APP>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, ob, cnt,
+  walk_backward<LPR, TEX, APP, kCap>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, ob, cnt,
                                a.g_dist != nullptr);
   __syncthreads();
   table_flush(tab, a.g, a.s.res * a.s.res, a.s.res);
