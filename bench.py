@@ -34,6 +34,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -64,12 +65,23 @@ KERNEL_SOURCES = ["include/voro.h"] + [
      "walk_impl.hpp")]
 
 
-def source_hash() -> str:
+def _code_only(text: str) -> str:
+    """The source with its comments and blank lines removed (counters depend
+    on the code, not on how it is commented).  String literals in these
+    sources hold no comment markers."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def source_hash(root: str = None) -> str:
+    """Hash of the code (comments stripped) of the sources the multi-view
+    kernels are compiled from; the committed counter summaries carry it."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
+        with open(os.path.join(root or ROOT, rel), "r", encoding="utf-8") as f:
             h.update(rel.encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
