@@ -201,6 +201,10 @@ struct FwdState {
   float T, Cr, Cg, Cb, t_in;
   float dP, dQ, dW, dA, s0;
   int cur, k;
+  // the record of cell cur, loaded as soon as cur is known (the exit
+  // decision of the previous step), so that its latency overlaps that
+  // step's texel lookup and compositing
+  Cell nc;
 };
 
 // false: nothing to walk (tmax <= 0 or an invalid start cell)
@@ -219,6 +223,7 @@ __device__ __forceinline__ bool fwd_begin(FwdState<APP>& st, const DevScene& s, 
     return false;
   }
   cnt.rays++;
+  st.nc = load_cell(s.cells, r.start);
   st.tp = ray_taps<APP>(r, s.res);
   if constexpr (APP == 2) sh3_basis(r.dx, r.dy, r.dz, st.Ysh);
   return true;
@@ -233,8 +238,9 @@ __device__ __forceinline__ bool fwd_step(FwdState<APP>& st, const DevScene& s,
                                          bool dist_on, const float4* lrow = nullptr) {
   const int cur = st.cur;
   const float t_in = st.t_in;
-  const Cell c = load_cell(s.cells, cur);
+  const Cell c = st.nc;
   const Exit ex = step_exit<LPR, E16>(s, w, r, c, cur, t_in, sub, lrow);
+  if (ex.next >= 0) st.nc = load_cell(s.cells, ex.next);
   cnt.redecide += ex.redecided ? 1u : 0u;
   cnt.deg += (uint32_t)c.deg;
   const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
@@ -391,10 +397,9 @@ __device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const W
   while (__any(alive)) {
     const float4* row = nullptr;
     if (wait == 0) {
-      // the row bounds for the staging; fwd_step takes the record again
-      // (the compiler keeps one load)
+      // the row bounds for the staging (the record fwd_step will use)
       Cell c;
-      if (alive) c = load_cell(s.cells, st.cur);
+      if (alive) c = st.nc;
       bool staged;
       row = stage_rows(s.edges, slab, alive, st.cur, c, lane, staged);
       if (staged) {
