@@ -180,15 +180,15 @@ __device__ __forceinline__ void write_ray_out(const ViewsArgs& a, const TileRay&
 // PERSIST: waves loop over the XCD-partitioned tile queue; otherwise each
 // wave of the grid takes one tile (workgroups renumbered per XCD) and the
 // hardware dispatcher balances the load.  One lane per ray walks with staged
-// edge rows (dynamic LDS: kStageBytesPerWave per wave) unless the edges are
-// ranked in half precision.  The persistent one-lane-per-ray exact walk is
+// edge rows (dynamic LDS: kStageBytesPerWave per wave), also when gathered
+// rows are ranked in half precision.  The persistent one-lane-per-ray exact walk is
 // held to 96 VGPRs, five waves per SIMD instead of four (the registers come
 // from the FP64 branch, the per-view focal length and the per-tile counters;
 // its few spills, 24 bytes per lane, sit outside the walk loop); the extra
 // wave hides more of the gathers' latency.
 template <int LPR, int APP, bool PERSIST, bool E16>
 struct FwdWaves {
-  static constexpr int value = (PERSIST && LPR == 1 && APP == 0 && !E16) ? 5 : 1;
+  static constexpr int value = (LPR == 1 && APP == 0 && (PERSIST ? !E16 : E16)) ? 5 : 1;
 };
 
 template <int LPR, int TEX, int APP, bool PERSIST, bool E16>
@@ -219,10 +219,10 @@ __global__ void __launch_bounds__(256)
     bool capped = false;
     TileRay tr;
     const bool has = tile_ray(a.ct, tile, 0, 0, grp, a.tile_w, a.tile_h, a.tile_w, a.tile_h, tr);
-    if constexpr (LPR == 1 && !E16) {
+    if constexpr (LPR == 1) {
       RayIn r{};
       if (has) r = views_ray(a, tr, &capped);
-      const RayOut out = walk_forward_staged<TEX, APP>(
+      const RayOut out = walk_forward_staged<TEX, APP, E16>(
           a.s, a.w, r, has, lane, slabs + wave * (kStageBytesPerWave / 16), nullptr, 0, cnt);
       if (has) write_ray_out<LPR>(a, tr, out);
     } else if (has) {

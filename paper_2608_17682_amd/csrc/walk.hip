@@ -144,7 +144,8 @@ struct RayArgs {
 };
 
 // One lane per ray walks with staged edge rows (dynamic LDS:
-// kStageBytesPerWave per wave) unless the edges are ranked in half precision.
+// kStageBytesPerWave per wave), also when gathered rows are ranked in half
+// precision.
 template <int LPR, int TEX, int APP, bool E16>
 __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
   extern __shared__ float4 slabs[];
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int ray = map_ray<LPR>(a.map, lb, wave, nwaves, grp);
   Counters cnt;
-  constexpr bool staged = LPR == 1 && !E16;
+  constexpr bool staged = LPR == 1;
   if (ray >= 0 || staged) {
     RayIn r{};
     if (ray >= 0) {
@@ -173,7 +174,7 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
                        ? a.cells_out + (size_t)ray * a.max_record
                        : nullptr;
     const RayOut out =
-        staged ? walk_forward_staged<TEX, APP>(a.s, a.w, r, ray >= 0, lane,
+        staged ? walk_forward_staged<TEX, APP, E16>(a.s, a.w, r, ray >= 0, lane,
                                                slabs + wave * (kStageBytesPerWave / 16), rec,
                                                a.max_record, cnt, a.dist_out != nullptr)
                : walk_forward<LPR, TEX, APP, E16>(a.s, a.w, r, sub, rec, a.max_record, cnt,
@@ -272,7 +273,8 @@ static void launch_ray_kernel(bool backward, const RayArgs& a, int blocks, int b
     const size_t lds = LPR == 1 ? (size_t)(block / 64) * kStageBytesPerWave : 0;
     if constexpr (LPR == 1) {
       if (a.w.edge16) {
-        hipLaunchKernelGGL((k_render_fwd<1, TEX, APP, true>), dim3(blocks), dim3(block), 0, st, a);
+        hipLaunchKernelGGL((k_render_fwd<1, TEX, APP, true>), dim3(blocks), dim3(block), lds, st,
+                           a);
         return;
       }
     }

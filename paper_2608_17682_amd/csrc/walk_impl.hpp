@@ -126,9 +126,10 @@ __device__ __forceinline__ void wg_stats_flush(const unsigned long long* s,
 
 // One step of the walk: the exit of cell `cur` entered at t_in.  lrow: the
 // cell's edge row staged in LDS by the wave (one lane per ray), or null to
-// gather it from global memory.  E16: rank the row from its half-precision
-// copy first (a template switch, so the exact walk's kernels do not carry
-// that code's registers).
+// gather it from global memory.  E16: rank a gathered row from its
+// half-precision copy first (a template switch, so the exact walk's kernels
+// do not carry that code's registers); a staged row is searched in FP32
+// either way, which reads it from LDS and costs less than the ranking.
 template <int LPR, bool E16 = false>
 __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w, const RayIn& r,
                                           const Cell& c, int cur, float t_in, int sub,
@@ -138,7 +139,7 @@ __device__ __forceinline__ Exit step_exit(const DevScene& s, const WalkParams& w
   const float qz = fmaf(t_in, r.dz, r.oz) - c.pz;
   Best b;
   bool searched = false;
-  if constexpr (LPR == 1 && E16) {
+  if constexpr (LPR == 1 && E16) if (!lrow) {
     // Rank in half precision.  When the bounds leave a single face that can
     // hold the smallest FP32 crossing, and every other face lies beyond the
     // tie window from it, that face's FP32 record gives exactly what the
@@ -381,7 +382,7 @@ __device__ __forceinline__ const float4* stage_rows(const float4* __restrict__ e
 // walk_forward with one lane per ray and staged rows.  Every lane of the
 // wave must call this (has_ray = false for lanes without a ray); slab: the
 // wave's kStageBytesPerWave of LDS.
-template <int TEX, int APP>
+template <int TEX, int APP, bool E16 = false>
 __device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const WalkParams& w,
                                                       const RayIn& r, bool has_ray, int lane,
                                                       float4* slab, int32_t* rec, int max_record,
@@ -413,9 +414,9 @@ __device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const W
     }
     if (alive) {
       if (row)
-        alive = !fwd_step<1, TEX, APP>(st, s, w, r, 0, rec, max_record, cnt, dist_on, row);
+        alive = !fwd_step<1, TEX, APP, E16>(st, s, w, r, 0, rec, max_record, cnt, dist_on, row);
       else
-        alive = !fwd_step<1, TEX, APP>(st, s, w, r, 0, rec, max_record, cnt, dist_on);
+        alive = !fwd_step<1, TEX, APP, E16>(st, s, w, r, 0, rec, max_record, cnt, dist_on);
     }
   }
   return fwd_end<APP>(st, walk, cnt);
