@@ -26,7 +26,8 @@ ellipsoid scene forward + backward through the autograd Function; the
 FP64 oracle timed on the host cores.
 
     python bench.py [--steps K] [--warmup W]
-    python bench.py --workload config5 --steps 1 --warmup 0   (one workload, for profiling)
+    python bench.py --workload config5 --steps 1 --warmup 0 --profile
+                                          (one workload, only its step's launches: profiling)
     python bench.py --copy-probe                              (1 GiB device copy only)
     python bench.py --summarise-counters OUT.json --kernel NAME --pmc DIR [DIR ...]
 """
@@ -100,22 +101,26 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def fwd_step_bytes(stats, texel_bytes):
+def fwd_step_bytes(stats, texel_bytes, stored=0):
     """Algorithmic bytes of a forward pass: per visited cell the cell record
     (xyz + sigma, 16 B), its adjacency bounds (8 B), per neighbour its id and
-    position (4 + 12 B) and 4 RGBA texels; per ray 44 B of ray in / colour out."""
+    position (4 + 12 B) and 4 RGBA texels; per ray 44 B of ray in / colour out;
+    8 B per stored exit (`stored` of the steps)."""
     return (float(stats["steps"]) * (16 + 8 + 4 * texel_bytes) + 16.0 * stats["degree_sum"]
-            + 44.0 * stats["rays"])
+            + 44.0 * stats["rays"] + 8.0 * stored)
 
 
-def bwd_step_bytes(stats, texel_bytes):
+def bwd_step_bytes(stats, texel_bytes, stored=0):
     """Algorithmic bytes of an adjoint pass: the forward's reads (the replay),
     plus per visited cell the gradient read-modify-writes of its density (4 B),
     the two sites of its exit face (2 x 12 B) and the RGB of its 4 texels
     (4 x 12 B), plus per ray the saved colour and transmittance and the
-    upstream gradient (32 B)."""
-    return (fwd_step_bytes(stats, texel_bytes) - 44.0 * stats["rays"]
-            + float(stats["steps"]) * (4 + 24 + 48) + 32.0 * stats["rays"])
+    upstream gradient (32 B).  A step whose exit was stored reads those 8 B
+    instead of its edge row (rows of the other steps taken at the mean degree)."""
+    steps = float(stats["steps"])
+    rows = 16.0 * stats["degree_sum"] * (1.0 - stored / max(1.0, steps))
+    return (steps * (16 + 8 + 4 * texel_bytes) + rows + 8.0 * stored
+            + steps * (4 + 24 + 48) + 32.0 * stats["rays"])
 
 
 def stats_dict(t):
@@ -262,8 +267,15 @@ def roofline_of(counters, ms, algo_bytes, kernel):
     return out
 
 
+# Steps per ray whose exits the headline's forward stores for its adjoint:
+# 7.7M rays x 256 x 8 B = 15.9 GB; the few rays that walk further (longest
+# about 300 cells here) have their later exits searched again.
+EXIT_STEPS = 256
+
+
 def bench_config5(scene, dev, args, timed):
-    """The headline: 4M sites, binary16 texels, 8 mixed views per launch, fwd + bwd."""
+    """The headline: 4M sites, binary16 texels, 8 mixed views per launch, fwd + bwd
+    (the forward stores each ray's first EXIT_STEPS exits for the adjoint)."""
     import torch
     from paper_2608_17682_amd import autotune, synth, voro
     cams = synth.config5_cameras(1.0)
@@ -279,8 +291,10 @@ def bench_config5(scene, dev, args, timed):
     ray = torch.empty((nr, 4), device=dev)
     st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
     ks = torch.empty(nr, dtype=torch.int32, device=dev)
-    voro.voro_render_views_fwd(ds, ccams, pf, rgb, T, ray, nsteps=ks, stats=st)
+    trace = torch.empty((EXIT_STEPS, nr, 2), dtype=torch.int32, device=dev)
+    voro.voro_render_views_fwd(ds, ccams, pf, rgb, T, ray, nsteps=ks, stats=st, trace=trace)
     stats = stats_dict(st)
+    stored = int(torch.clamp(ks, max=EXIT_STEPS).sum())
     rays = stats["rays"]   # fisheye pixels outside the image circle emit no ray
     kv = ks[ks > 0].float()
     kq = torch.quantile(kv[torch.randperm(kv.numel(), device=dev)[:1 << 20]],
@@ -290,26 +304,38 @@ def bench_config5(scene, dev, args, timed):
     gd = torch.zeros(ds.n, device=dev)
     gt = torch.zeros(tuple(ds.texels.shape), device=dev)
 
-    def fwd():
+    def fwd(tr):
         voro.voro_prepare(ds)
-        voro.voro_render_views_fwd(ds, ccams, pf, rgb, T, ray)
+        voro.voro_render_views_fwd(ds, ccams, pf, rgb, T, ray, trace=tr)
 
     def bwd():
-        voro.voro_render_views_bwd(ds, ccams, rgb, T, ray, g, None, pb, gs, gd, gt)
+        voro.voro_render_views_bwd(ds, ccams, rgb, T, ray, g, None, pb, gs, gd, gt, trace=trace)
 
     def step():
         gs.zero_()
         gd.zero_()
         gt.zero_()
-        fwd()
+        fwd(trace)
         bwd()
 
     secs = timed(step, args.steps, args.warmup)
-    sf = timed(fwd, args.steps, 1)
-    fwd_ms = launch_ms(torch, lambda: voro.voro_render_views_fwd(ds, ccams, pf, rgb, T, ray), 3)
+    fwdt_ms = launch_ms(
+        torch, lambda: voro.voro_render_views_fwd(ds, ccams, pf, rgb, T, ray, trace=trace), 3)
     bwd_ms = launch_ms(torch, bwd, 3)
+    sf = fwd_ms = None
+    if not args.profile:
+        # the forward alone, as an inference pass renders (no stored exits);
+        # left out of profiled runs so that every forward launch they see is
+        # the step's
+        sf = timed(lambda: fwd(None), args.steps, 1)
+        fwd_ms = launch_ms(torch, lambda: voro.voro_render_views_fwd(ds, ccams, pf, rgb, T, ray),
+                           3)
+    del trace
     res = {"rays_per_step": rays, "secs": secs, "fwd_secs": sf, "stats": stats,
-           "fwd_launch_ms": fwd_ms, "bwd_launch_ms": bwd_ms,
+           "fwd_launch_ms": fwd_ms, "fwd_stored_launch_ms": fwdt_ms, "bwd_launch_ms": bwd_ms,
+           "stored_exits": {"steps_per_ray": EXIT_STEPS, "stored": stored,
+                            "searched_again": int(stats["steps"]) - stored,
+                            "bytes": EXIT_STEPS * nr * 8},
            "cells_per_ray": {"mean": round(stats["steps"] / max(1, rays), 2),
                              "p50": float(kq[0]), "p99": float(kq[1]),
                              "max": int(ks.max())},
@@ -511,8 +537,9 @@ def bench_config3(scene, dev, args, timed):
     """2M sites on 20 ellipsoid surfaces, one 1280x840 interior pinhole view;
     forward + backward through the autograd Functions (FP32), upstream dL/dRGB
     ~ N(0,1).  A step: gradients reset (as zero_grad(set_to_none=True) does),
-    prepare, the forward launch, dL/dsigma through sigma = exp(rho), the
-    backward launch.  Headline render_views (in-kernel ray generation, tuned
+    prepare, the forward launch (storing each ray's first EXIT_STEPS exits),
+    dL/dsigma through sigma = exp(rho), the backward launch (reading them).
+    Headline render_views (in-kernel ray generation, tuned
     launches); also render over explicit rays."""
     import torch
     from paper_2608_17682_amd import autotune, synth, voro
@@ -535,7 +562,8 @@ def bench_config3(scene, dev, args, timed):
 
     def step_views():
         reset()
-        rgb, T = render_views(sites, torch.exp(rho), tex, ds.nbr_off, ds.nbr_idx, ccam, pf, pb)
+        rgb, T = render_views(sites, torch.exp(rho), tex, ds.nbr_off, ds.nbr_idx, ccam, pf, pb,
+                              stored_exits=EXIT_STEPS)
         (rgb * g).sum().backward()
 
     def step_explicit(dist=False):
@@ -681,6 +709,8 @@ def main():
     ap.add_argument("--workload", choices=["all", "config5", "config2", "config3", "config1"],
                     default="all", help="one workload only (no oracle legs), e.g. for profiling")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="run only the timed step's launches (for rocprofv3)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--summarise-counters", metavar="OUT_JSON")
@@ -760,16 +790,24 @@ def main():
         cb = load_counters("bwd")
         if cb:
             cb["_path"] = COUNTERS["bwd"]
-        roof = roofline_of(cb, r5["bwd_launch_ms"], bwd_step_bytes(st, 8),
-                           "k_views_bwd (adjoint, 8 views, persistent queue)")
+        sx = r5["stored_exits"]
+        roof = roofline_of(cb, r5["bwd_launch_ms"], bwd_step_bytes(st, 8, sx["stored"]),
+                           "k_views_bwd (adjoint reading stored exits, 8 views, persistent "
+                           "queue)")
         cf = load_counters("fwd")
         if cf:
             cf["_path"] = COUNTERS["fwd"]
-        extras["config5_fwd_only"] = {
-            "mrays_s": round(rays * args.steps / r5["fwd_secs"] / 1e6, 2),
-            "ms_per_step": round(r5["fwd_secs"] * 1e3 / args.steps, 3),
-            "roofline": roofline_of(cf, r5["fwd_launch_ms"], fwd_step_bytes(st, 8),
-                                    "k_views_fwd (8 views, persistent queue)")}
+        extras["config5_fwd_in_step"] = {
+            "launch_ms": round(r5["fwd_stored_launch_ms"], 3),
+            "roofline": roofline_of(cf, r5["fwd_stored_launch_ms"],
+                                    fwd_step_bytes(st, 8, sx["stored"]),
+                                    "k_views_fwd (storing exits, 8 views, persistent queue)")}
+        extras["config5_stored_exits"] = sx
+        if r5["fwd_secs"] is not None:
+            extras["config5_fwd_only"] = {
+                "mrays_s": round(rays * args.steps / r5["fwd_secs"] / 1e6, 2),
+                "ms_per_step": round(r5["fwd_secs"] * 1e3 / args.steps, 3),
+                "launch_ms": round(r5["fwd_launch_ms"], 3)}
         extras["config5_cells_per_ray"] = r5["cells_per_ray"]
         extras["config5_fp64_redecisions_per_step"] = st["fp64_redecide"]
         extras["config5_adjoint_share_of_step"] = round(r5["bwd_launch_ms"] / ms_per_step, 3)
@@ -785,7 +823,8 @@ def main():
                                    "launch (2 pinhole 1280x840, 2 equidistant fisheye 180deg "
                                    "1024x1024, 2 rolling shutter 960x540, 2 thin lens 640x480 x4 "
                                    "samples) on a radius-3 orbit, tmax 8; step = zero grads + "
-                                   "prepare + forward launch + adjoint launch",
+                                   "prepare + forward launch (storing each ray's first "
+                                   f"{EXIT_STEPS} exits) + adjoint launch (reading them)",
                        "rays_per_step": rays, "sites": 4_000_000, "texels": "f16",
                        "morton": True, "launch_fwd": r5["launch_fwd"],
                        "launch_bwd": r5["launch_bwd"]},

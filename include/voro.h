@@ -353,13 +353,22 @@ voro_status voro_gen_rays(const voro_camera* cams, int32_t V, float* o, float* d
  *   ray_rgbT [n_rays,4] float out: per-ray (rgb, T); required when a view
  *   has spp > 1 (the backward needs it), may be NULL otherwise.
  *   nsteps [n_rays] int32 out or NULL.
+ *   trace [trace_cap][n_rays][2] int32 out or NULL: the exit of each ray's
+ *   step k < trace_cap (Sec. 3.1: the bisector crossing that ends the
+ *   segment in the k-th visited cell) at trace[k][ray] = {exit parameter t
+ *   as the bit pattern of its FP32 value, next cell (-1: none)}; entries at
+ *   and beyond a ray's step count are left untouched.  Caller-owned device
+ *   memory of trace_cap * n_rays * 8 bytes, 8-byte aligned; trace_cap >= 1
+ *   when trace is given (else VORO_EINVAL), ignored when it is NULL.  Handed
+ *   to voro_render_views_bwd, it spares the adjoint the exit searches.
  * params.tile_w/tile_h/lanes_per_ray pick the tiling; img_w, max_record are
  * ignored.  Requires voro_prepare.
  */
 voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                                   const voro_camera* cams, int32_t V, const voro_params* params,
                                   float* rgb, float* T, float* ray_rgbT, int32_t* nsteps,
-                                  uint64_t* stats, void* stream);
+                                  int32_t* trace, int32_t trace_cap, uint64_t* stats,
+                                  void* stream);
 
 /*
  * Adjoint of voro_render_views_fwd (one launch; workgroups walk workgroup
@@ -368,13 +377,20 @@ voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_b
  * and g_T [n_pixels] (or NULL) the upstream gradients; a thin-lens pixel's
  * gradient is shared equally by its samples.  Accumulates (+=) like
  * voro_render_bwd.
+ *   trace, trace_cap: NULL, or the exits voro_render_views_fwd stored for
+ *   the same scene, cameras and walk parameters (same trace_cap): the
+ *   adjoint then takes steps k < trace_cap from it and searches only the
+ *   steps beyond; the gradients are those of the search.  A stored next
+ *   cell outside [0, n_sites) ends that ray's walk (never read out of
+ *   bounds); any other mismatch gives wrong gradients, as mismatched rgb/T
+ *   would.  trace_cap >= 1 when trace is given (else VORO_EINVAL).
  */
 voro_status voro_render_views_bwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                                   const voro_camera* cams, int32_t V, const voro_params* params,
                                   const float* rgb, const float* T, const float* ray_rgbT,
-                                  const float* g_rgb, const float* g_T, float* g_sites,
-                                  float* g_density, float* g_texels, uint64_t* stats,
-                                  void* stream);
+                                  const int32_t* trace, int32_t trace_cap, const float* g_rgb,
+                                  const float* g_T, float* g_sites, float* g_density,
+                                  float* g_texels, uint64_t* stats, void* stream);
 
 /*
  * For callers that cannot allocate (code under HIP graph capture, tight
@@ -385,7 +401,7 @@ voro_status voro_render_views_bwd(const voro_scene* scene, void* ws, size_t ws_b
  * instead of the workspace.  The workspace is only read: it must hold the
  * records voro_prepare wrote (voro_workspace_size bytes always suffice).
  * Outputs, arguments, validation and results are those of
- * voro_render_views_fwd.  V above VORO_MAX_VIEWS (the scratch's maximum) is
+ * voro_render_views_fwd without a trace.  V above VORO_MAX_VIEWS (the scratch's maximum) is
  * rejected with VORO_EINVAL.  Nothing is allocated: no hipMalloc, hipFree or
  * allocating library routine is called (the first call on a device looks
  * the array's device address up).  Every call on one GPU shares that GPU's

@@ -58,11 +58,17 @@ class VoroRender(torch.autograd.Function):
 
 class VoroRenderViews(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sites, density, texels, nbr_off, nbr_idx, cams, params_fwd, params_bwd):
+    def forward(ctx, sites, density, texels, nbr_off, nbr_idx, cams, params_fwd, params_bwd,
+                stored_exits):
         ds = voro.DeviceScene(sites.detach().contiguous(), density.detach().contiguous(),
                               nbr_off, nbr_idx, texels.detach().contiguous())
         voro.voro_prepare(ds)
-        rgb, T, ray_rgbT = voro.voro_render_views_fwd(ds, cams, params_fwd)
+        trace = None
+        if stored_exits > 0:
+            nr, _ = voro.voro_camera_counts(list(cams))
+            trace = torch.empty((stored_exits, nr, 2), dtype=torch.int32, device=sites.device)
+        rgb, T, ray_rgbT = voro.voro_render_views_fwd(ds, cams, params_fwd, trace=trace)
+        ctx.trace = trace
         ctx.ds = ds
         ctx.cams = cams
         ctx.params = params_bwd
@@ -78,10 +84,11 @@ class VoroRenderViews(torch.autograd.Function):
             g_rgb = torch.zeros_like(rgb)
         gs, gd, gt = voro.voro_render_views_bwd(
             ctx.ds, ctx.cams, rgb, T, ctx.ray_rgbT, g_rgb.contiguous(),
-            None if g_T is None else g_T.contiguous(), ctx.params)
+            None if g_T is None else g_T.contiguous(), ctx.params, trace=ctx.trace)
+        ctx.trace = None
         if ctx.tex_dtype != torch.float32:
             gt = gt.to(ctx.tex_dtype)
-        return gs, gd, gt, None, None, None, None, None
+        return gs, gd, gt, None, None, None, None, None, None
 
 
 # walk parameters: they decide the cell sequence and the colour, so the
@@ -121,17 +128,23 @@ def backward_params(params_fwd, params_bwd=None):
 
 
 def render_views(sites, density, texels, nbr_off, nbr_idx, cams, params_fwd=None,
-                 params_bwd=None):
+                 params_bwd=None, stored_exits=0):
     """Differentiable render of camera views (voro_camera list or objects with
     the camera attributes); pixels of all views concatenated in order.
-    params_bwd supplies only the adjoint's launch shape (see backward_params)."""
+    params_bwd supplies only the adjoint's launch shape (see backward_params).
+    stored_exits > 0: the forward keeps each ray's first stored_exits exits
+    (8 bytes per ray and step, until the backward) and the adjoint reads them
+    instead of searching those steps again."""
     cams = voro.camera_array(cams)
     params_fwd = params_fwd or voro.default_params()
     params_bwd = backward_params(params_fwd, params_bwd)
-    if _wants_grad(sites, density, texels):
+    wants = _wants_grad(sites, density, texels)
+    if wants:
         _check_differentiable(params_fwd)
+    if stored_exits < 0:
+        raise ValueError("stored_exits must be >= 0")
     return VoroRenderViews.apply(sites, density, texels, nbr_off, nbr_idx, cams, params_fwd,
-                                 params_bwd)
+                                 params_bwd, int(stored_exits) if wants else 0)
 
 
 def render(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params=None,

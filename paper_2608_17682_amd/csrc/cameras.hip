@@ -78,7 +78,20 @@ struct ViewsArgs {
   const float* g_T;
   Grads g;
   unsigned long long* stats;
+  // stored exits, [trace_cap][n_rays] (null: the adjoint searches every step)
+  int2* trace;
+  int trace_cap;
+  unsigned n_rays;
 };
+
+// the stored exits of one ray (none for a lane without a ray)
+__device__ __forceinline__ ExitTrace ray_trace(const ViewsArgs& a, bool has, int ray) {
+  ExitTrace x;
+  x.p = a.trace && has ? a.trace + ray : nullptr;
+  x.stride = a.n_rays;
+  x.cap = a.trace_cap;
+  return x;
+}
 
 struct Centers {
   float c[3 * VORO_MAX_VIEWS];
@@ -223,11 +236,13 @@ __global__ void __launch_bounds__(256)
       RayIn r{};
       if (has) r = views_ray(a, tr, &capped);
       const RayOut out = walk_forward_staged<TEX, APP, E16>(
-          a.s, a.w, r, has, lane, slabs + wave * (kStageBytesPerWave / 16), nullptr, 0, cnt);
+          a.s, a.w, r, has, lane, slabs + wave * (kStageBytesPerWave / 16), nullptr, 0, cnt,
+          false, ray_trace(a, has, tr.ray));
       if (has) write_ray_out<LPR>(a, tr, out);
     } else if (has) {
       const RayIn r = views_ray(a, tr, &capped);
-      const RayOut out = walk_forward<LPR, TEX, APP, E16>(a.s, a.w, r, sub, nullptr, 0, cnt);
+      const RayOut out = walk_forward<LPR, TEX, APP, E16>(a.s, a.w, r, sub, nullptr, 0, cnt,
+                                                          false, ray_trace(a, true, tr.ray));
       if (sub == 0) write_ray_out<LPR>(a, tr, out);
     }
     if (a.stats) {
@@ -294,7 +309,8 @@ __global__ void __launch_bounds__(256) k_views_fwd_refill(ViewsArgs a) {
         if (q >= pool) break;
         continue;
       }
-      if (active && fwd_step<1, TEX, APP, E16>(st, a.s, a.w, r, 0, nullptr, 0, cnt, false)) {
+      if (active && fwd_step<1, TEX, APP, E16>(st, a.s, a.w, r, 0, nullptr, 0, cnt, false, nullptr,
+                                               ray_trace(a, true, tr.ray))) {
         write_ray_out<1>(a, tr, fwd_end<APP>(st, true, cnt));
         active = false;
       }
@@ -391,7 +407,8 @@ __global__ void __launch_bounds__(256)
     // the whole wave walks its tile together (gradient records merge across
     // lanes); its counters go to the workgroup's LDS stats after each unit
     Counters cnt;
-    walk_backward<LPR, TEX, APP, kCap>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, ob, cnt);
+    walk_backward<LPR, TEX, APP, kCap>(a.s, a.w, r, u, has, sub, lane, a.g, &tab, ob, cnt, false,
+                                       ray_trace(a, has, tr.ray));
     if (a.stats) {
       if constexpr (PERSIST) {
         tile_counters_to_lds(cnt, has && sub == 0, false, lane, s_stats);
@@ -593,7 +610,7 @@ static voro_status views_common(bool backward, const voro_scene* scene, const vo
                                 size_t ws_bytes, const ViewsScratch* static_scratch,
                                 const voro_camera* cams, int32_t V, const voro_params* params,
                                 ViewsArgs& a, int64_t* n_rays, int64_t* n_pixels, bool* any_spp,
-                                void* stream) {
+                                int32_t* trace, int32_t trace_cap, void* stream) {
   voro_status st;
   if ((st = check_scene(scene)) != VORO_OK) return st;
   static_assert(kViewsScratchPartials <= 4096, "counter region");
@@ -615,6 +632,9 @@ static voro_status views_common(bool backward, const voro_scene* scene, const vo
   *any_spp = spp;
   if ((st = check_device()) != VORO_OK) return st;
   const Launch L = resolve_launch(params);
+  a.trace = reinterpret_cast<int2*>(trace);
+  a.trace_cap = trace ? trace_cap : 0;
+  a.n_rays = (unsigned)*n_rays;
   a.counters = reinterpret_cast<unsigned int*>(sc.base + kViewsScratchCounters);
   int32_t* centers = reinterpret_cast<int32_t*>(sc.base + kViewsScratchCenters);
   float* origins = reinterpret_cast<float*>(sc.base + kViewsScratchOrigins);
@@ -737,7 +757,7 @@ voro_status voro_render_views_fwd_noalloc(const voro_scene* scene, const void* w
   a.stats = reinterpret_cast<unsigned long long*>(stats);
   bool any_spp = false;
   st = views_common(false, scene, ws, ws_bytes, &sc, cams, V, params, a, &nr, &np, &any_spp,
-                    stream);
+                    nullptr, 0, stream);
   if (st != VORO_OK) return st;
   if (any_spp) {
     const int n = (int)np;
@@ -762,12 +782,23 @@ voro_status voro_gen_rays(const voro_camera* cams, int32_t V, float* o, float* d
   return check_launch("voro_gen_rays");
 }
 
+// trace arguments of the multi-view calls
+static voro_status check_trace(const int32_t* trace, int32_t trace_cap) {
+  if (!trace) return VORO_OK;
+  if (trace_cap < 1) return fail(VORO_EINVAL, "trace_cap = %d: must be >= 1 with a trace", trace_cap);
+  if (!aligned(trace, 8)) return fail(VORO_EINVAL, "trace must be 8-byte aligned");
+  return VORO_OK;
+}
+
 voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                                   const voro_camera* cams, int32_t V, const voro_params* params,
                                   float* rgb, float* T, float* ray_rgbT, int32_t* nsteps,
-                                  uint64_t* stats, void* stream) {
+                                  int32_t* trace, int32_t trace_cap, uint64_t* stats,
+                                  void* stream) {
   if (!rgb || !T) return fail(VORO_EINVAL, "rgb and T must not be NULL");
   if (ray_rgbT && !aligned(ray_rgbT, 16)) return fail(VORO_EINVAL, "ray_rgbT must be 16-byte aligned");
+  voro_status st0 = check_trace(trace, trace_cap);
+  if (st0 != VORO_OK) return st0;
   ViewsArgs a = {};
   a.rgb = rgb;
   a.T = T;
@@ -783,7 +814,7 @@ voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_b
     if (cams[v].spp > 1 && !ray_rgbT)
       return fail(VORO_EINVAL, "ray_rgbT is required when a view has spp > 1");
   st = views_common(false, scene, ws, ws_bytes, nullptr, cams, V, params, a, &nr, &np, &any_spp,
-                    stream);
+                    trace, trace_cap, stream);
   if (st != VORO_OK) return st;
   if (any_spp) {
     const int n = (int)np;
@@ -797,10 +828,12 @@ voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_b
 voro_status voro_render_views_bwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                                   const voro_camera* cams, int32_t V, const voro_params* params,
                                   const float* rgb, const float* T, const float* ray_rgbT,
-                                  const float* g_rgb, const float* g_T, float* g_sites,
-                                  float* g_density, float* g_texels, uint64_t* stats,
-                                  void* stream) {
+                                  const int32_t* trace, int32_t trace_cap, const float* g_rgb,
+                                  const float* g_T, float* g_sites, float* g_density,
+                                  float* g_texels, uint64_t* stats, void* stream) {
   if (!rgb || !T || !g_rgb) return fail(VORO_EINVAL, "rgb, T and g_rgb must not be NULL");
+  voro_status st0 = check_trace(trace, trace_cap);
+  if (st0 != VORO_OK) return st0;
   if (!g_sites || !g_density || !g_texels)
     return fail(VORO_EINVAL, "gradient outputs must not be NULL");
   if (ray_rgbT && !aligned(ray_rgbT, 16)) return fail(VORO_EINVAL, "ray_rgbT must be 16-byte aligned");
@@ -823,7 +856,7 @@ voro_status voro_render_views_bwd(const voro_scene* scene, void* ws, size_t ws_b
   if (scene && ws) a.g.cell = cell_grads(scene, ws);
   bool any_spp = false;
   st = views_common(true, scene, ws, ws_bytes, nullptr, cams, V, params, a, &nr, &np, &any_spp,
-                    stream);
+                    const_cast<int32_t*>(trace), trace_cap, stream);
   if (st != VORO_OK) return st;
   return launch_fold_cell_grads(scene, ws, g_sites, g_density, (hipStream_t)stream);
 }

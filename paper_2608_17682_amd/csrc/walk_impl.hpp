@@ -230,17 +230,29 @@ __device__ __forceinline__ bool fwd_begin(FwdState<APP>& st, const DevScene& s, 
   return true;
 }
 
+// Stored exits of a ray: step k's exit (parameter t by bit pattern, next
+// cell) at p[k * stride] for k < cap, written by the forward and read by the
+// adjoint instead of searching the step's edge row again (null: none).
+struct ExitTrace {
+  int2* p;
+  unsigned stride;
+  int cap;
+};
+
 // One visited cell (lrow: its edge row staged in LDS, or null); true when
 // the ray has ended.
 template <int LPR, int TEX, int APP, bool E16 = false>
 __device__ __forceinline__ bool fwd_step(FwdState<APP>& st, const DevScene& s,
                                          const WalkParams& w, const RayIn& r, int sub,
                                          int32_t* rec, int max_record, Counters& cnt,
-                                         bool dist_on, const float4* lrow = nullptr) {
+                                         bool dist_on, const float4* lrow = nullptr,
+                                         const ExitTrace& xt = {}) {
   const int cur = st.cur;
   const float t_in = st.t_in;
   const Cell c = st.nc;
   const Exit ex = step_exit<LPR, E16>(s, w, r, c, cur, t_in, sub, lrow);
+  if (xt.p && sub == 0 && st.k < xt.cap)
+    xt.p[(size_t)st.k * xt.stride] = make_int2(__float_as_int(ex.t), ex.next);
   if (ex.next >= 0) st.nc = load_cell(s.cells, ex.next);
   cnt.redecide += ex.redecided ? 1u : 0u;
   cnt.deg += (uint32_t)c.deg;
@@ -316,11 +328,12 @@ template <int LPR, int TEX, int APP, bool E16 = false>
 __device__ __forceinline__ RayOut walk_forward(const DevScene& s, const WalkParams& w,
                                                const RayIn& r, int sub, int32_t* rec,
                                                int max_record, Counters& cnt,
-                                               bool dist_on = false) {
+                                               bool dist_on = false, const ExitTrace& xt = {}) {
   FwdState<APP> st;
   const bool walk = fwd_begin<APP>(st, s, r, cnt);
   if (walk)
-    while (!fwd_step<LPR, TEX, APP, E16>(st, s, w, r, sub, rec, max_record, cnt, dist_on)) {
+    while (!fwd_step<LPR, TEX, APP, E16>(st, s, w, r, sub, rec, max_record, cnt, dist_on,
+                                         nullptr, xt)) {
     }
   return fwd_end<APP>(st, walk, cnt);
 }
@@ -386,7 +399,8 @@ template <int TEX, int APP, bool E16 = false>
 __device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const WalkParams& w,
                                                       const RayIn& r, bool has_ray, int lane,
                                                       float4* slab, int32_t* rec, int max_record,
-                                                      Counters& cnt, bool dist_on = false) {
+                                                      Counters& cnt, bool dist_on = false,
+                                                      const ExitTrace& xt = {}) {
   FwdState<APP> st;
   const bool walk = has_ray && fwd_begin<APP>(st, s, r, cnt);
   bool alive = walk;
@@ -414,9 +428,10 @@ __device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const W
     }
     if (alive) {
       if (row)
-        alive = !fwd_step<1, TEX, APP, E16>(st, s, w, r, 0, rec, max_record, cnt, dist_on, row);
+        alive = !fwd_step<1, TEX, APP, E16>(st, s, w, r, 0, rec, max_record, cnt, dist_on, row, xt);
       else
-        alive = !fwd_step<1, TEX, APP, E16>(st, s, w, r, 0, rec, max_record, cnt, dist_on);
+        alive =
+            !fwd_step<1, TEX, APP, E16>(st, s, w, r, 0, rec, max_record, cnt, dist_on, nullptr, xt);
     }
   }
   return fwd_end<APP>(st, walk, cnt);
@@ -736,7 +751,7 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
                                               const Upstream& u, bool has_ray, int sub, int lane,
                                               const Grads& g, const GradTable<CAP>* tab,
                                               const Outbox& ob, Counters& cnt,
-                                              bool dist_on = false) {
+                                              bool dist_on = false, const ExitTrace& xt = {}) {
   const int R = s.res;
   const int RR = R * R;
   constexpr int MAPS = APP ? 2 : 1;
@@ -774,7 +789,17 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
     float v_mr = 0.0f, v_mg = 0.0f, v_mb = 0.0f;
     if (active) {
       const Cell c = load_cell(s.cells, cur);
-      const Exit ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
+      Exit ex;
+      if (xt.p && k < xt.cap) {
+        // the forward's exit of this step (a next cell outside the scene,
+        // which only a trace from another walk could hold, ends the ray)
+        const int2 e = xt.p[(size_t)k * xt.stride];
+        ex.t = __int_as_float(e.x);
+        ex.next = e.y >= 0 && e.y < s.n ? e.y : -1;
+        ex.redecided = false;
+      } else {
+        ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
+      }
       cnt.redecide += ex.redecided ? 1u : 0u;
       cnt.deg += (uint32_t)c.deg;
       const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);

@@ -108,10 +108,10 @@ def lib():
             "voro_camera_counts": ([P(voro_camera), i32, P(i64), P(i64)], i32),
             "voro_gen_rays": ([P(voro_camera), i32, vp, vp, vp, vp], i32),
             "voro_render_views_fwd": ([P(voro_scene), vp, ctypes.c_size_t, P(voro_camera), i32,
-                                       P(voro_params), vp, vp, vp, vp, vp, vp], i32),
+                                       P(voro_params), vp, vp, vp, vp, vp, i32, vp, vp], i32),
             "voro_render_views_bwd": ([P(voro_scene), vp, ctypes.c_size_t, P(voro_camera), i32,
-                                       P(voro_params), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
-                                      i32),
+                                       P(voro_params), vp, vp, vp, vp, i32, vp, vp, vp, vp, vp,
+                                       vp, vp], i32),
             "voro_render_views_fwd_noalloc": ([P(voro_scene), vp, ctypes.c_size_t,
                                                P(voro_camera), i32, P(voro_params), vp, vp, vp,
                                                vp, vp, vp], i32),
@@ -384,11 +384,26 @@ def voro_gen_rays(cams, device="cuda", stream=None):
     return o, d, tm
 
 
+def _trace_args(trace, nr):
+    """(pointer, cap) of a stored-exit buffer: int32 [cap, n_rays, 2] or None."""
+    if trace is None:
+        return None, 0
+    import torch
+    if (trace.dtype != torch.int32 or trace.dim() != 3 or trace.shape[1] != nr
+            or trace.shape[2] != 2 or not trace.is_contiguous()):
+        raise ValueError(f"trace must be a contiguous int32 tensor [cap, {nr}, 2], got "
+                         f"{trace.dtype} {tuple(trace.shape)}")
+    return trace, int(trace.shape[0])
+
+
 def voro_render_views_fwd(ds: DeviceScene, cams, params=None, rgb=None, T=None, ray_rgbT=None,
-                          nsteps=None, stats=None, stream=None):
+                          nsteps=None, stats=None, stream=None, trace=None):
+    """trace: None, or int32 [cap, n_rays, 2] that receives each ray's first
+    cap exits for voro_render_views_bwd."""
     import torch
     arr = camera_array(cams)
     nr, npx = voro_camera_counts(list(arr))
+    trace, cap = _trace_args(trace, nr)
     dev = ds.sites.device
     rgb = torch.empty((npx, 3), dtype=torch.float32, device=dev) if rgb is None else rgb
     T = torch.empty(npx, dtype=torch.float32, device=dev) if T is None else T
@@ -398,7 +413,8 @@ def voro_render_views_fwd(ds: DeviceScene, cams, params=None, rgb=None, T=None, 
     sc = ds.c()
     _check(lib().voro_render_views_fwd(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, arr, len(arr),
                                        ctypes.byref(p), _ptr(rgb), _ptr(T), _ptr(ray_rgbT),
-                                       _ptr(nsteps), _ptr(stats), _stream(stream)),
+                                       _ptr(nsteps), _ptr(trace), cap, _ptr(stats),
+                                       _stream(stream)),
            "voro_render_views_fwd")
     return rgb, T, ray_rgbT
 
@@ -418,9 +434,13 @@ def voro_render_views_fwd_noalloc(ds: DeviceScene, cams, params, rgb, T, ray_rgb
 
 
 def voro_render_views_bwd(ds: DeviceScene, cams, rgb, T, ray_rgbT, g_rgb, g_T=None, params=None,
-                          g_sites=None, g_density=None, g_texels=None, stats=None, stream=None):
+                          g_sites=None, g_density=None, g_texels=None, stats=None, stream=None,
+                          trace=None):
+    """trace: None (every exit is searched again) or the forward's stored exits."""
     import torch
     arr = camera_array(cams)
+    nr, _ = voro_camera_counts(list(arr))
+    trace, cap = _trace_args(trace, nr)
     dev = ds.sites.device
     if g_sites is None:
         g_sites = torch.zeros((ds.n, 3), dtype=torch.float32, device=dev)
@@ -432,7 +452,8 @@ def voro_render_views_bwd(ds: DeviceScene, cams, rgb, T, ray_rgbT, g_rgb, g_T=No
     sc = ds.c()
     _check(lib().voro_render_views_bwd(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, arr, len(arr),
                                        ctypes.byref(p), _ptr(rgb), _ptr(T), _ptr(ray_rgbT),
-                                       _ptr(g_rgb), _ptr(g_T), _ptr(g_sites), _ptr(g_density),
+                                       _ptr(trace), cap, _ptr(g_rgb), _ptr(g_T), _ptr(g_sites),
+                                       _ptr(g_density),
                                        _ptr(g_texels), _ptr(stats), _stream(stream)),
            "voro_render_views_bwd")
     return g_sites, g_density, g_texels

@@ -191,6 +191,32 @@ def test_camera_validation(L):
     assert L.voro_camera_counts(many, len(many), None, None) == voro.VORO_EINVAL
 
 
+def test_views_trace_validation(L):
+    # a stored-exit buffer needs a capacity of at least one step and 8-byte
+    # alignment; both are checked before anything touches a device
+    from paper_2608_17682_amd import synth
+    arr = voro.camera_array(synth.config5_cameras(scale=0.05)[:1])
+    s = fake_scene()
+    p = voro.default_params()
+    A = 0x10000
+    args = (ctypes.byref(s), A, 1 << 20, arr, 1, ctypes.byref(p), A, A, None, None)
+    assert L.voro_render_views_fwd(*args, A, 0, None, None) == voro.VORO_EINVAL
+    assert "trace_cap" in voro.last_error()
+    assert L.voro_render_views_fwd(*args, A + 4, 16, None, None) == voro.VORO_EINVAL
+    assert "aligned" in voro.last_error()
+    bargs = (ctypes.byref(s), A, 1 << 20, arr, 1, ctypes.byref(p), A, A, None)
+    assert L.voro_render_views_bwd(*bargs, A, -3, A, None, A, A, A, None,
+                                   None) == voro.VORO_EINVAL
+    assert "trace_cap" in voro.last_error()
+    import torch
+    with pytest.raises(ValueError):
+        voro._trace_args(torch.zeros((4, 7, 2), dtype=torch.int64), 7)
+    with pytest.raises(ValueError):
+        voro._trace_args(torch.zeros((4, 6, 2), dtype=torch.int32), 7)
+    t = torch.zeros((4, 7, 2), dtype=torch.int32)
+    assert voro._trace_args(t, 7)[1] == 4 and voro._trace_args(None, 7) == (None, 0)
+
+
 def test_cast_and_reorder_validation(L):
     assert L.voro_cast_texels(0x1000, 0x2000, 16, 0, None) == voro.VORO_EINVAL
     assert L.voro_cast_texels(None, None, 0, 1, None) == 0

@@ -19,6 +19,12 @@ def test_byte_model_per_unit():
     # the adjoint replays the reads, adds 76 B of gradient updates per cell and
     # 32 B per ray instead of 44
     assert bench.bwd_step_bytes(stats, 8) == 10 * (24 + 32 + 76) + 16 * 150 + 32 * 2
+    # stored exits: 8 B written per stored step; the adjoint reads them in place
+    # of those steps' edge rows (the rest at the mean degree, 15 here)
+    assert bench.fwd_step_bytes(stats, 8, 6) == bench.fwd_step_bytes(stats, 8) + 48
+    assert bench.bwd_step_bytes(stats, 8, 6) == pytest.approx(
+        10 * (24 + 32 + 76) + 16 * 15 * 4 + 8 * 6 + 32 * 2)
+    assert bench.bwd_step_bytes(stats, 8, 10) == 10 * (24 + 32 + 76) + 80 + 32 * 2
 
 
 def _counters(hbm, valu, busy, cycles=1.0e6):

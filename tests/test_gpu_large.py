@@ -150,8 +150,10 @@ def test_config3_adjoint_sampled_rays(dev, c3):
                        "config3 explicit")
 
 
-def test_config3_benchmark_autograd_step_matches_oracle(dev, c3):
-    announce("config3: the benchmarked autograd render_views step, sampled pixels")
+@pytest.mark.parametrize("stored_exits", [0, 256])
+def test_config3_benchmark_autograd_step_matches_oracle(dev, c3, stored_exits):
+    announce(f"config3: the benchmarked autograd render_views step (stored exits: "
+             f"{stored_exits}), sampled pixels")
     g = c3.g
     ok = ~g["degenerate"]
     gimg = np.zeros((c3.cam.n_pixels, 3), np.float32)
@@ -159,7 +161,8 @@ def test_config3_benchmark_autograd_step_matches_oracle(dev, c3):
     sites = c3.ds.sites.clone().requires_grad_(True)
     dens = c3.ds.density.clone().requires_grad_(True)
     tex = c3.ds.texels.clone().requires_grad_(True)
-    rgb, T = render_views(sites, dens, tex, c3.ds.nbr_off, c3.ds.nbr_idx, [c3.cam], c3.pf, c3.pb)
+    rgb, T = render_views(sites, dens, tex, c3.ds.nbr_off, c3.ds.nbr_idx, [c3.cam], c3.pf, c3.pb,
+                          stored_exits=stored_exits)
     sd = ~g["stop_degenerate"]
     px = g["pixels"]
     assert np.abs(rgb.detach().cpu().numpy()[px] - g["rgb"])[sd].max() <= 1e-4
@@ -219,8 +222,10 @@ def test_config5_benchmark_launch_forward(dev, c5):
     assert T[c5.off[2]] == 1.0 and np.all(rgb[c5.off[2]] == 0)
 
 
-def test_config5_benchmark_launch_adjoint(dev, c5):
-    announce("config5: the benchmarked adjoint launch, upstream on the gradient pixels only")
+@pytest.mark.parametrize("cap", [0, 256])
+def test_config5_benchmark_launch_adjoint(dev, c5, cap):
+    announce(f"config5: the benchmarked adjoint launch (stored exits: {cap} steps), upstream "
+             "on the gradient pixels only")
     g = c5.g
     npx = int(c5.off[-1])
     g_all = synth.upstream(npx, 5, with_gT=False)[0]
@@ -229,9 +234,12 @@ def test_config5_benchmark_launch_adjoint(dev, c5):
         if use:
             gimg[c5.off[v] + p] = g_all[c5.off[v] + p]
     assert g["px_grad"].sum() >= 0.85 * (6 * 32 + 2 * 8)
-    rgb, T, ray = voro.voro_render_views_fwd(c5.ds, c5.cams, c5.pf)
+    nr = sum(cam.n_rays for cam in c5.cams)
+    trace = torch.empty((cap, nr, 2), dtype=torch.int32, device=dev) if cap else None
+    rgb, T, ray = voro.voro_render_views_fwd(c5.ds, c5.cams, c5.pf, trace=trace)
     gs, gd, gt = voro.voro_render_views_bwd(c5.ds, c5.cams, rgb, T, ray, to_dev(gimg, dev), None,
-                                            c5.pb)
+                                            c5.pb, trace=trace)
+    del trace
     assert_grads_match(g, gs.cpu().numpy(), gd.cpu().numpy(), gt.cpu().numpy(), c5.inv,
                        "config5 views")
 

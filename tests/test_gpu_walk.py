@@ -360,6 +360,70 @@ def test_views_bwd_equals_explicit(dev, c1):
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), name
 
 
+@pytest.mark.parametrize("lpr,schedule,cap", [(1, voro.SCHEDULE_PERSISTENT, 512),
+                                              (1, voro.SCHEDULE_GRID, 3),
+                                              (1, voro.SCHEDULE_REFILL, 7),
+                                              (4, voro.SCHEDULE_PERSISTENT, 5)])
+def test_views_stored_exits(dev, c1, lpr, schedule, cap):
+    # The forward's stored exits are the walk's own (each step's next cell is
+    # the cell the explicit-ray walk visits next); they change no forward
+    # output, and the adjoint that reads them (searching only past the cap)
+    # gives the gradients of the adjoint that searches every step.
+    cams = synth.config5_cameras(scale=0.05) + synth.motion_blur_cameras(scale=0.04, spp=3)
+    for cm in cams:
+        cm.tmax = 4.0
+    nr = [cm.n_rays for cm in cams]
+    R = sum(nr)
+    npx = sum(cm.n_pixels for cm in cams)
+    g_rgb, g_T = synth.upstream(npx, 7)
+    p = voro.default_params()
+    p.lanes_per_ray = lpr
+    p.schedule = schedule
+    announce(f"stored exits lpr={lpr} schedule={schedule} cap={cap}")
+    ns0 = torch.empty(R, dtype=torch.int32, device=dev)
+    rgb0, T0, ray0 = voro.voro_render_views_fwd(c1.ds, cams, p, nsteps=ns0)
+    trace = torch.full((cap, R, 2), -7, dtype=torch.int32, device=dev)
+    ns1 = torch.empty(R, dtype=torch.int32, device=dev)
+    rgb1, T1, ray1 = voro.voro_render_views_fwd(c1.ds, cams, p, nsteps=ns1, trace=trace)
+    assert torch.equal(rgb0, rgb1) and torch.equal(T0, T1) and torch.equal(ray0, ray1)
+    assert torch.equal(ns0, ns1)
+    # the explicit-ray walk's visited cells
+    O, D, TM = voro.voro_gen_rays(cams, dev)
+    centres = to_dev(f32([cm.c2w[:, 3] for cm in cams]), dev)
+    cc = voro.voro_locate_origins(c1.ds, centres)
+    hint = torch.cat([cc[i:i + 1].expand(n) for i, n in enumerate(nr)]).contiguous()
+    S = voro.voro_locate_origins(c1.ds, O, hint=hint)
+    pe = voro.default_params()
+    pe.max_record = 256
+    K = torch.empty(R, dtype=torch.int32, device=dev)
+    cells = torch.empty((R, 256), dtype=torch.int32, device=dev)
+    voro.voro_render_fwd(c1.ds, O, D, TM, S, pe, nsteps=K, cells=cells)
+    K, cells, tr = K.cpu().numpy(), cells.cpu().numpy(), trace.cpu().numpy()
+    assert np.array_equal(K, ns1.cpu().numpy()) and K.max() <= 256
+    walked = 0
+    for i in range(R):
+        k = int(K[i])
+        m = min(k, cap)
+        # steps 0..m-2 lead to the next visited cell; the last stored step
+        # to the next one or to none
+        assert np.array_equal(tr[:max(m - 1, 0), i, 1], cells[i, 1:max(m, 1)]), i
+        if m > 0:
+            assert -1 <= tr[m - 1, i, 1] < c1.ds.n
+            assert np.isfinite(tr[:m - 1, i, 0].view(np.float32)).all()
+        assert (tr[m:, i] == -7).all(), i  # steps not walked are left untouched
+        walked += k > cap
+    if cap < 10:
+        assert walked > 0  # some rays go past the stored steps
+    g1, gT1 = to_dev(g_rgb, dev), to_dev(g_T, dev)
+    ga = voro.voro_render_views_bwd(c1.ds, cams, rgb0, T0, ray0, g1, gT1, p)
+    gb = voro.voro_render_views_bwd(c1.ds, cams, rgb1, T1, ray1, g1, gT1, p, trace=trace)
+    for a, b, name in zip(ga, gb, ("sites", "density", "texels")):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.isfinite(b).all()
+        # same terms, different atomic order: FP32 summation differences only
+        assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(a).max()), name
+
+
 def test_distortion_fwd_matches_oracle(dev, c1):
     R = len(c1.o)
     dist = torch.empty((R, 3), dtype=torch.float32, device=dev)
