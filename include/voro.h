@@ -77,11 +77,13 @@ enum {
 enum {
   VORO_STAT_RAYS = 0,          /* rays walked (tmax > 0 and valid start) */
   VORO_STAT_STEPS = 1,         /* cells visited, summed over rays (sum K(r)) */
-  VORO_STAT_DEGREE_SUM = 2,    /* Delaunay degree of visited cells, summed */
+  VORO_STAT_DEGREE_SUM = 2,    /* Delaunay degree of visited cells whose exit was
+                                  searched (every step, unless a stored exit
+                                  stood in for the search), summed */
   VORO_STAT_MAX_STEPS = 3,     /* rays cut by params.max_steps */
   VORO_STAT_NAN = 4,           /* rays whose transmittance became NaN */
   VORO_STAT_BAD_START = 5,     /* rays whose start cell was out of range */
-  VORO_STAT_FP64_REDECIDE = 6, /* exit faces re-decided in FP64 */
+  VORO_STAT_FP64_REDECIDE = 6, /* exit faces re-decided in FP64 (in searched steps) */
   VORO_STAT_SKIPPED = 7,       /* texel lookups skipped (weight < skip_w) */
   VORO_STAT_BAD_CSR = 8,       /* adjacency rows/entries found malformed by voro_prepare */
   VORO_STAT_LOCATE_CAP = 9,    /* nearest-site walks stopped by their step cap */

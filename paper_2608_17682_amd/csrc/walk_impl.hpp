@@ -233,6 +233,7 @@ __device__ __forceinline__ bool fwd_begin(FwdState<APP>& st, const DevScene& s, 
 // Stored exits of a ray: step k's exit (parameter t by bit pattern, next
 // cell) at p[k * stride] for k < cap, written by the forward and read by the
 // adjoint instead of searching the step's edge row again (null: none).
+using i32x2 = int __attribute__((ext_vector_type(2)));
 struct ExitTrace {
   int2* p;
   unsigned stride;
@@ -251,8 +252,12 @@ __device__ __forceinline__ bool fwd_step(FwdState<APP>& st, const DevScene& s,
   const float t_in = st.t_in;
   const Cell c = st.nc;
   const Exit ex = step_exit<LPR, E16>(s, w, r, c, cur, t_in, sub, lrow);
-  if (xt.p && sub == 0 && st.k < xt.cap)
-    xt.p[(size_t)st.k * xt.stride] = make_int2(__float_as_int(ex.t), ex.next);
+  if (xt.p && sub == 0 && st.k < xt.cap) {
+    // streamed out (only the adjoint reads it back): a non-temporal store
+    // leaves the caches to the walk's records
+    const i32x2 e = {__float_as_int(ex.t), ex.next};
+    __builtin_nontemporal_store(e, reinterpret_cast<i32x2*>(xt.p + (size_t)st.k * xt.stride));
+  }
   if (ex.next >= 0) st.nc = load_cell(s.cells, ex.next);
   cnt.redecide += ex.redecided ? 1u : 0u;
   cnt.deg += (uint32_t)c.deg;
@@ -766,6 +771,10 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
   float T = 1.0f, Pr = 0.0f, Pg = 0.0f, Pb = 0.0f, t_in = 0.0f;
   float dW = 0.0f, dA = 0.0f, dGW = 0.0f, s0 = 0.0f;  // distortion prefix sums
   int cur = active ? r.start : 0;
+  // the current cell's position and density: loaded with the previous
+  // step's exit (a step with a stored exit needs nothing else of its cell)
+  float4 here = active ? s.cells[2 * (size_t)cur] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+
   int k = 0;
   // previous cell's record (emitted one step late): its texel multipliers
   // and, for APP = 1, its surface taps
@@ -788,7 +797,7 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
     int v_key = -1;  // APP = 1: this cell's view-map record
     float v_mr = 0.0f, v_mg = 0.0f, v_mb = 0.0f;
     if (active) {
-      const Cell c = load_cell(s.cells, cur);
+      Cell c;
       Exit ex;
       if (xt.p && k < xt.cap) {
         // the forward's exit of this step (a next cell outside the scene,
@@ -797,9 +806,17 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         ex.t = __int_as_float(e.x);
         ex.next = e.y >= 0 && e.y < s.n ? e.y : -1;
         ex.redecided = false;
+        c.px = here.x;
+        c.py = here.y;
+        c.pz = here.z;
+        c.sigma = here.w;
+        c.off = 0;
+        c.deg = 0;
       } else {
+        c = load_cell(s.cells, cur);
         ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
       }
+      const float4 pn = ex.next >= 0 ? s.cells[2 * (size_t)ex.next] : here;
       cnt.redecide += ex.redecided ? 1u : 0u;
       cnt.deg += (uint32_t)c.deg;
       const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
@@ -912,7 +929,6 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         }
         if (ex.t < r.tmax && ex.next >= 0) {
           // exit end: along the exit face (cur -> next)
-          const float4 pn = s.cells[2 * (size_t)ex.next];
           const float nx = pn.x - c.px;
           const float ny = pn.y - c.py;
           const float nz = pn.z - c.pz;
@@ -991,6 +1007,7 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
       } else {
         t_in = fmaxf(t_in, fminf(ex.t, r.tmax));
         cur = ex.next;
+        here = pn;
       }
     }
     emit_records<LPR, 0, APP == 1, CAP>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane,

@@ -415,8 +415,19 @@ def test_views_stored_exits(dev, c1, lpr, schedule, cap):
     if cap < 10:
         assert walked > 0  # some rays go past the stored steps
     g1, gT1 = to_dev(g_rgb, dev), to_dev(g_T, dev)
-    ga = voro.voro_render_views_bwd(c1.ds, cams, rgb0, T0, ray0, g1, gT1, p)
-    gb = voro.voro_render_views_bwd(c1.ds, cams, rgb1, T1, ray1, g1, gT1, p, trace=trace)
+    sa = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    sb = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    ga = voro.voro_render_views_bwd(c1.ds, cams, rgb0, T0, ray0, g1, gT1, p, stats=sa)
+    gb = voro.voro_render_views_bwd(c1.ds, cams, rgb1, T1, ray1, g1, gT1, p, trace=trace,
+                                    stats=sb)
+    # the same steps; edge rows read only where no exit was stored
+    i_steps, i_deg = voro.STAT_NAMES.index("steps"), voro.STAT_NAMES.index("degree_sum")
+    sa, sb = sa.cpu().numpy(), sb.cpu().numpy()
+    assert sa[i_steps] == sb[i_steps] == int(K.sum())
+    if cap >= K.max():
+        assert sb[i_deg] == 0
+    else:
+        assert 0 < sb[i_deg] < sa[i_deg]
     for a, b, name in zip(ga, gb, ("sites", "density", "texels")):
         a, b = a.cpu().numpy(), b.cpu().numpy()
         assert np.isfinite(b).all()
