@@ -579,23 +579,29 @@ def bench_config3(scene, dev, args, timed):
 
     st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
     voro.voro_prepare(ds)
-    voro.voro_render_views_fwd(ds, ccam, pf, stats=st)
+    tr = torch.empty((EXIT_STEPS, cam.n_rays, 2), dtype=torch.int32, device=dev)
+    voro.voro_render_views_fwd(ds, ccam, pf, stats=st, trace=tr)   # as the step's forward
+    del tr
     stats = stats_dict(st)
     steps = max(2, args.steps // 2)
     s = timed(step_views, steps, 1)
-    se = timed(step_explicit, steps, 1)
-    sd = timed(lambda: step_explicit(True), steps, 1)
-    fwd_s = timed(lambda: voro.voro_render_views_fwd(ds, ccam, pf), steps, 1)
 
     def mr(x):
         return round(cam.n_rays * steps / x / 1e6, 2)
-    return {"workload": "ellipsoids2M: 1.8M sites on 20 ellipsoid surfaces (sigma 50) + 200k "
-                        "uniform [-4,4]^3 (sigma 0.01), 8x8 f32 texels, 1280x840 interior "
-                        "pinhole, tmax 14, fwd+bwd via torch.autograd.Function",
-            "fwd_bwd_mrays_s": mr(s), "fwd_bwd_explicit_rays_mrays_s": mr(se),
-            "fwd_bwd_explicit_rays_with_distortion_mrays_s": mr(sd),
-            "fwd_kernel_mrays_s": mr(fwd_s), "ms_per_step": round(s * 1e3 / steps, 3),
-            "mean_cells_per_ray": round(stats["steps"] / max(1, stats["rays"]), 2)}
+    res = {"workload": "ellipsoids2M: 1.8M sites on 20 ellipsoid surfaces (sigma 50) + 200k "
+                       "uniform [-4,4]^3 (sigma 0.01), 8x8 f32 texels, 1280x840 interior "
+                       "pinhole, tmax 14, fwd+bwd via torch.autograd.Function",
+           "fwd_bwd_mrays_s": mr(s), "ms_per_step": round(s * 1e3 / steps, 3),
+           "mean_cells_per_ray": round(stats["steps"] / max(1, stats["rays"]), 2)}
+    if args.profile:   # profiled runs: only the render_views step's launches
+        return res
+    se = timed(step_explicit, steps, 1)
+    sd = timed(lambda: step_explicit(True), steps, 1)
+    fwd_s = timed(lambda: voro.voro_render_views_fwd(ds, ccam, pf), steps, 1)
+    res.update({"fwd_bwd_explicit_rays_mrays_s": mr(se),
+                "fwd_bwd_explicit_rays_with_distortion_mrays_s": mr(sd),
+                "fwd_kernel_mrays_s": mr(fwd_s)})
+    return res
 
 
 def bench_config1(dev, args, timed):

@@ -772,8 +772,12 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
   float dW = 0.0f, dA = 0.0f, dGW = 0.0f, s0 = 0.0f;  // distortion prefix sums
   int cur = active ? r.start : 0;
   // the current cell's position and density: loaded with the previous
-  // step's exit (a step with a stored exit needs nothing else of its cell)
-  float4 here = active ? s.cells[2 * (size_t)cur] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  // step's exit (a step with a stored exit needs nothing else of its cell).
+  // Single map only: the full model's adjoint would lose a wave per SIMD to
+  // the registers it holds.
+  constexpr bool kCarry = APP == 0;
+  float4 here = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (kCarry && active) here = s.cells[2 * (size_t)cur];
 
   int k = 0;
   // previous cell's record (emitted one step late): its texel multipliers
@@ -799,13 +803,16 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
     if (active) {
       Cell c;
       Exit ex;
-      if (xt.p && k < xt.cap) {
+      const bool stored = xt.p && k < xt.cap;
+      if (stored) {
         // the forward's exit of this step (a next cell outside the scene,
         // which only a trace from another walk could hold, ends the ray)
         const int2 e = xt.p[(size_t)k * xt.stride];
         ex.t = __int_as_float(e.x);
         ex.next = e.y >= 0 && e.y < s.n ? e.y : -1;
         ex.redecided = false;
+      }
+      if (kCarry && stored) {
         c.px = here.x;
         c.py = here.y;
         c.pz = here.z;
@@ -814,9 +821,10 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         c.deg = 0;
       } else {
         c = load_cell(s.cells, cur);
-        ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
+        if (!stored) ex = step_exit<LPR>(s, w, r, c, cur, t_in, sub);
       }
-      const float4 pn = ex.next >= 0 ? s.cells[2 * (size_t)ex.next] : here;
+      float4 pn = here;
+      if constexpr (kCarry) pn = ex.next >= 0 ? s.cells[2 * (size_t)ex.next] : here;
       cnt.redecide += ex.redecided ? 1u : 0u;
       cnt.deg += (uint32_t)c.deg;
       const Segment sg = segment(ex.t, r.tmax, t_in, c.sigma);
@@ -929,6 +937,7 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
         }
         if (ex.t < r.tmax && ex.next >= 0) {
           // exit end: along the exit face (cur -> next)
+          if constexpr (!kCarry) pn = s.cells[2 * (size_t)ex.next];
           const float nx = pn.x - c.px;
           const float ny = pn.y - c.py;
           const float nz = pn.z - c.pz;
@@ -1007,7 +1016,7 @@ __device__ __forceinline__ void walk_backward(const DevScene& s, const WalkParam
       } else {
         t_in = fmaxf(t_in, fminf(ex.t, r.tmax));
         cur = ex.next;
-        here = pn;
+        if constexpr (kCarry) here = pn;
       }
     }
     emit_records<LPR, 0, APP == 1, CAP>(e_key, e_ds, e_px, e_py, e_pz, e_tp, e_mr, e_mg, e_mb, lane,
