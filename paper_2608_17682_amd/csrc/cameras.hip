@@ -197,7 +197,7 @@ __device__ __forceinline__ void write_ray_out(const ViewsArgs& a, const TileRay&
 // rows are ranked in half precision.  The persistent one-lane-per-ray exact walk is
 // held to 96 VGPRs, five waves per SIMD instead of four (the registers come
 // from the FP64 branch, the per-view focal length and the per-tile counters;
-// its few spills, 24 bytes per lane, sit outside the walk loop); the extra
+// its few spills, 48 bytes per lane, sit outside the walk loop); the extra
 // wave hides more of the gathers' latency.
 template <int LPR, int APP, bool PERSIST, bool E16>
 struct FwdWaves {
