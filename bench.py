@@ -348,7 +348,8 @@ def bench_config5(scene, dev, args, timed):
 
 def bench_config2(scene, cams, dev, args, timed, oracle2):
     """100k-site shell scene, 8 x 800x800 poses per step: the texel-precision
-    comparison and the inference variants."""
+    comparison and the inference variants; forward + backward with each
+    frame's exits stored for its adjoint."""
     import torch
     from paper_2608_17682_amd import autotune, synth, voro
     ds0 = voro.device_scene(scene, dev)
@@ -365,9 +366,14 @@ def bench_config2(scene, cams, dev, args, timed, oracle2):
     out = {"workload": "shell100k: 100k sites (70% unit-sphere shell, sigma 50; 30% uniform "
                        "[-2,2]^3, sigma 0.01), 8x8 texels, 8 orbit poses of 800x800 per step"}
 
-    def frame(i, p, dscene, out_rgb=rgb, out_T=T, stats=None, nsteps=None):
+    def frame(i, p, dscene, out_rgb=rgb, out_T=T, stats=None, nsteps=None, trace=None):
         voro.voro_render_views_fwd(dscene, [ccams[i]], p, rgb=out_rgb, T=out_T, stats=stats,
-                                   nsteps=nsteps)
+                                   nsteps=nsteps, trace=trace)
+
+    # forward + backward: each frame's forward stores its rays' first
+    # EXIT_STEPS exits for that frame's adjoint (all poses have one size)
+    trace = torch.empty((EXIT_STEPS, voro.voro_camera_counts([ccams[0]])[0], 2),
+                        dtype=torch.int32, device=dev)
 
     def step(dscene, p):
         voro.voro_prepare(dscene)
@@ -405,9 +411,9 @@ def bench_config2(scene, cams, dev, args, timed, oracle2):
             gt.zero_()
             voro.voro_prepare(dsc)
             for i in range(N_POSES):
-                frame(i, params, dsc)
+                frame(i, params, dsc, trace=trace)
                 voro.voro_render_views_bwd(dsc, [ccams[i]], rgb, T, None, g_rgb, None, params_bwd,
-                                           gs, gd, gt)
+                                           gs, gd, gt, trace=trace)
         s = timed(fb, kb, 1)
         out[f"fwd_bwd_{name}_mrays_s"] = mrays(s, kb)
         del gs, gd, gt
@@ -507,8 +513,9 @@ def bench_config2(scene, cams, dev, args, timed, oracle2):
     def fbf():
         voro.voro_prepare(dsf)
         for i in range(N_POSES):
-            frame(i, pf, dsf)
-            voro.voro_render_views_bwd(dsf, [ccams[i]], rgb, T, None, g_rgb, None, pfb, gs, gd, gt)
+            frame(i, pf, dsf, trace=trace)
+            voro.voro_render_views_bwd(dsf, [ccams[i]], rgb, T, None, g_rgb, None, pfb, gs, gd, gt,
+                                       trace=trace)
     s = timed(fbf, kb, 1)
     fa["fwd_bwd_f32_mrays_s"] = mrays(s, kb)
     out["full_appearance"] = fa
