@@ -154,6 +154,12 @@ def test_full_views_equal_explicit(dev, cf):
     g_rgb, g_T = synth.upstream(npx, 5)
     gv = voro.voro_render_views_bwd(cf.ds, cams, rgb_v, T_v, ray_v, to_dev(g_rgb, dev),
                                     to_dev(g_T, dev), p)
+    # the same adjoint reading the forward's first 3 exits of each ray (the
+    # rest searched): the full model reloads each cell's record itself
+    trace = torch.empty((3, sum(nr), 2), dtype=torch.int32, device=dev)
+    voro.voro_render_views_fwd(cf.ds, cams, p, trace=trace)
+    gx = voro.voro_render_views_bwd(cf.ds, cams, rgb_v, T_v, ray_v, to_dev(g_rgb, dev),
+                                    to_dev(g_T, dev), p, trace=trace)
     gr, gt_ = [], []
     off = 0
     for cm in cams:
@@ -163,9 +169,10 @@ def test_full_views_equal_explicit(dev, cf):
         off += cm.n_pixels
     ge = voro.voro_render_bwd(cf.ds, O, D, TM, S, rgb_e, T_e, to_dev(np.concatenate(gr), dev),
                               to_dev(np.concatenate(gt_), dev), p)
-    for a, b, name in zip(gv, ge, ("sites", "density", "texels")):
-        a, b = a.cpu().numpy(), b.cpu().numpy()
+    for a, x, b, name in zip(gv, gx, ge, ("sites", "density", "texels")):
+        a, x, b = a.cpu().numpy(), x.cpu().numpy(), b.cpu().numpy()
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), name
+        assert np.abs(x - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), name
 
 
 @pytest.mark.parametrize("dtype", ["float16", "bfloat16"])

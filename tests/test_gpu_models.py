@@ -98,19 +98,23 @@ def dense_texel_grads(g):
     return out.reshape(-1, maps, res, res, 3)
 
 
+@pytest.mark.parametrize("cap", [0, 256])
 @pytest.mark.parametrize("schedule", SCHEDULES)
-def test_full_model_adjoint_under_contention(cm, schedule):
-    announce(f"models: full-model adjoint, 32x32 block upstream, schedule {schedule}")
+def test_full_model_adjoint_under_contention(cm, schedule, cap):
+    announce(f"models: full-model adjoint, 32x32 block upstream, schedule {schedule}, "
+             f"stored exits {cap}")
     ds, inv = cm.scenes["full"]
     g = cm.g
     p = voro.default_params(appearance=1, schedule=schedule)
-    rgb, T, ray = voro.voro_render_views_fwd(ds, [cm.cam], p)
+    trace = (torch.empty((cap, cm.cam.n_rays, 2), dtype=torch.int32, device=cm.dev)
+             if cap else None)
+    rgb, T, ray = voro.voro_render_views_fwd(ds, [cm.cam], p, trace=trace)
     npx = cm.cam.n_pixels
     gimg = np.zeros((npx, 3), np.float32)
     use = g["grad_rays"]
     gimg[g["pixels"][use]] = g["g_rgb"][use]
     gs, gd, gt = voro.voro_render_views_bwd(ds, [cm.cam], rgb, T, ray, to_dev(gimg, cm.dev),
-                                            None, p)
+                                            None, p, trace=trace)
     gs, gd, gt = gs.cpu().numpy(), gd.cpu().numpy(), gt.cpu().numpy()
     assert gt.shape == (ds.n, 2, ds.tex_res, ds.tex_res, 4)
     k = inv[g["grad_cells"]]

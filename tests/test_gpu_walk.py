@@ -435,6 +435,38 @@ def test_views_stored_exits(dev, c1, lpr, schedule, cap):
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(a).max()), name
 
 
+def test_views_stored_exit_outside_the_scene_ends_the_ray(dev, c1):
+    # A stored next cell outside [0, n) (a buffer from another walk) is never
+    # read: the adjoint ends that ray's walk there, so every ray here stops
+    # after its first cell and only first-cell gradients appear.
+    cams = synth.config5_cameras(scale=0.05)[:2]
+    for cm in cams:
+        cm.tmax = 4.0
+    R = sum(cm.n_rays for cm in cams)
+    npx = sum(cm.n_pixels for cm in cams)
+    p = voro.default_params()
+    announce("stored exits: next cells outside the scene")
+    rgb, T, ray = voro.voro_render_views_fwd(c1.ds, cams, p)
+    trace = torch.empty((4, R, 2), dtype=torch.int32, device=dev)
+    trace[..., 0] = torch.tensor([1.0], dtype=torch.float32).view(torch.int32).item()
+    trace[..., 1] = c1.ds.n + 5
+    trace[1, :, 1] = -9
+    g = to_dev(synth.upstream(npx, 3, with_gT=False)[0], dev)
+    gs, gd, gt = voro.voro_render_views_bwd(c1.ds, cams, rgb, T, ray, g, None, p, trace=trace)
+    st = torch.zeros(voro.STAT_COUNT, dtype=torch.int64, device=dev)
+    voro.voro_render_views_bwd(c1.ds, cams, rgb, T, ray, g, None, p, trace=trace, stats=st)
+    st = st.cpu().numpy()
+    rays = int(st[voro.STAT_NAMES.index("rays")])
+    assert rays > 0 and int(st[voro.STAT_NAMES.index("steps")]) == rays
+    for a in (gs, gd, gt):
+        assert torch.isfinite(a).all()
+    # the start cells (one per camera centre) are the only cells touched
+    touched = torch.nonzero(gd).flatten().cpu().numpy()
+    centres = to_dev(f32([cm.c2w[:, 3] for cm in cams]), dev)
+    starts = set(voro.voro_locate_origins(c1.ds, centres).cpu().numpy().tolist())
+    assert set(touched.tolist()) <= starts
+
+
 def test_distortion_fwd_matches_oracle(dev, c1):
     R = len(c1.o)
     dist = torch.empty((R, 3), dtype=torch.float32, device=dev)
