@@ -578,7 +578,8 @@ def bench_config3(scene, dev, args, timed):
         O, D, TM = voro.voro_gen_rays(ccam, dev)
         S = voro.voro_locate_origins(ds, O[:1]).expand(O.shape[0]).contiguous()
         out = render(sites, torch.exp(rho), tex, ds.nbr_off, ds.nbr_idx, O, D, TM, S,
-                     voro.default_params(img_w=cam.width), distortion=dist)
+                     voro.default_params(img_w=cam.width), distortion=dist,
+                     stored_exits=EXIT_STEPS)
         loss = (out[0] * g).sum()
         if dist:   # the training objective with the distortion regulariser (Sec. 5.3)
             loss = loss + 0.01 * out[2].sum()

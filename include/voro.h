@@ -289,6 +289,9 @@ voro_status voro_locate_origins(const voro_scene* scene, const void* ws, size_t 
  *         eq. distortion-loss) sum_{k,l} w_k w_l |sbar_k - sbar_l| +
  *         1/3 sum_k w_k^2 ds_k over its segments, s(t) = 1 - 1/(1+t), then
  *         sum_k w_k sbar_k and sum_k w_k (kept for voro_render_bwd)
+ *   trace [trace_cap][R][2] int32 out or NULL: each ray's first trace_cap
+ *         exits, laid out and validated as for voro_render_views_fwd, for
+ *         voro_render_bwd
  * Rays with tmax <= 0 return rgb = 0, T = 1, K = 0.  Start cells out of
  * range return rgb = 0, T = 1 and are counted.  Requires voro_prepare.
  */
@@ -296,14 +299,17 @@ voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_b
                             const float* o, const float* d, const float* tmax,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
                             float* rgb, float* T, int32_t* nsteps, int32_t* cells, float* dist,
-                            uint64_t* stats, void* stream);
+                            int32_t* trace, int32_t trace_cap, uint64_t* stats, void* stream);
 
 /*
  * Adjoint of voro_render_fwd for L = sum_r g_rgb[r].rgb[r] + g_T[r] T[r]
  * (+ g_dist[r] L_dist[r]).
  * Replays each ray's walk (same code, same cell sequence) and recovers the
  * back-to-front colour suffix from the saved forward totals rgb and T, so
- * nothing per step is stored between the passes.  Accumulates (+=) into
+ * nothing per step needs storing between the passes; with `trace` (the
+ * exits voro_render_fwd stored for the same rays, scene and walk
+ * parameters) the steps it holds are taken from it instead of searched,
+ * as in voro_render_views_bwd.  Accumulates (+=) into
  *   g_sites [N,3], g_density [N] (dL/dsigma), g_texels [N,R,R,4] float
  *   ([N,2,R,R,4] with tex_maps = 2; A channel untouched), whatever the
  *   texel storage type.  Texel gradients are added with FP32 atomics;
@@ -324,8 +330,8 @@ voro_status voro_render_bwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
                             const float* rgb, const float* T, const float* g_rgb,
                             const float* g_T, const float* dist, const float* g_dist,
-                            float* g_sites, float* g_density, float* g_texels, uint64_t* stats,
-                            void* stream);
+                            const int32_t* trace, int32_t trace_cap, float* g_sites,
+                            float* g_density, float* g_texels, uint64_t* stats, void* stream);
 
 /* ------------------------------------------------------------ cameras */
 

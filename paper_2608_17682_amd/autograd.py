@@ -7,8 +7,10 @@ texels, nbr_off, nbr_idx, cameras)`` returns per-pixel (rgb [P,3], T [P])
 for up to 16 cameras generated in-kernel (one launch each way).  Both are
 differentiable with respect to the site positions, the densities sigma and
 the texels; rays, cameras and adjacency are not.  The forward runs
-voro_prepare + the forward walk; the backward replays each ray's walk
-instead of storing it.  Parameterise sigma = exp(rho) in torch (Sec. 5.4)
+voro_prepare + the forward walk; the backward replays each ray's walk,
+searching every exit again or, with stored_exits = n > 0, reading the first n
+exits of each ray that the forward stored (8 bytes per ray and step, held
+until the backward).  Parameterise sigma = exp(rho) in torch (Sec. 5.4)
 and autograd supplies dL/drho = sigma dL/dsigma.
 """
 from __future__ import annotations
@@ -21,13 +23,16 @@ from . import voro
 class VoroRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params,
-                with_dist):
+                with_dist, stored_exits):
         ds = voro.DeviceScene(sites.detach().contiguous(), density.detach().contiguous(),
                               nbr_off, nbr_idx, texels.detach().contiguous())
         voro.voro_prepare(ds)
         dist = (torch.empty((o.shape[0], 3), dtype=torch.float32, device=o.device)
                 if with_dist else None)
-        rgb, T = voro.voro_render_fwd(ds, o, d, tmax, start, params, dist=dist)
+        trace = (torch.empty((stored_exits, o.shape[0], 2), dtype=torch.int32, device=o.device)
+                 if stored_exits > 0 else None)
+        rgb, T = voro.voro_render_fwd(ds, o, d, tmax, start, params, dist=dist, trace=trace)
+        ctx.trace = trace
         ctx.ds = ds
         ctx.params = params
         ctx.tex_dtype = texels.dtype
@@ -50,10 +55,12 @@ class VoroRender(torch.autograd.Function):
             dist_in, g_dist = None, None
         gs, gd, gt = voro.voro_render_bwd(
             ds, o, d, tmax, start, rgb, T, g_rgb.contiguous(),
-            None if g_T is None else g_T.contiguous(), ctx.params, dist=dist_in, g_dist=g_dist)
+            None if g_T is None else g_T.contiguous(), ctx.params, dist=dist_in, g_dist=g_dist,
+            trace=ctx.trace)
+        ctx.trace = None
         if ctx.tex_dtype != torch.float32:
             gt = gt.to(ctx.tex_dtype)
-        return gs, gd, gt, None, None, None, None, None, None, None, None
+        return gs, gd, gt, None, None, None, None, None, None, None, None, None
 
 
 class VoroRenderViews(torch.autograd.Function):
@@ -148,13 +155,16 @@ def render_views(sites, density, texels, nbr_off, nbr_idx, cams, params_fwd=None
 
 
 def render(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params=None,
-           distortion=False):
+           distortion=False, stored_exits=0):
     """Differentiable render of explicit rays; see the module docstring.  With
     distortion=True also returns each ray's distortion loss (Sec. 5.3), [R],
-    differentiable like the colour."""
+    differentiable like the colour.  stored_exits: as for render_views."""
     if params is None:
         params = voro.default_params()
-    if _wants_grad(sites, density, texels):
+    wants = _wants_grad(sites, density, texels)
+    if wants:
         _check_differentiable(params)
+    if stored_exits < 0:
+        raise ValueError("stored_exits must be >= 0")
     return VoroRender.apply(sites, density, texels, nbr_off, nbr_idx, o, d, tmax, start, params,
-                            bool(distortion))
+                            bool(distortion), int(stored_exits) if wants else 0)

@@ -782,14 +782,6 @@ voro_status voro_gen_rays(const voro_camera* cams, int32_t V, float* o, float* d
   return check_launch("voro_gen_rays");
 }
 
-// trace arguments of the multi-view calls
-static voro_status check_trace(const int32_t* trace, int32_t trace_cap) {
-  if (!trace) return VORO_OK;
-  if (trace_cap < 1) return fail(VORO_EINVAL, "trace_cap = %d: must be >= 1 with a trace", trace_cap);
-  if (!aligned(trace, 8)) return fail(VORO_EINVAL, "trace must be 8-byte aligned");
-  return VORO_OK;
-}
-
 voro_status voro_render_views_fwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                                   const voro_camera* cams, int32_t V, const voro_params* params,
                                   float* rgb, float* T, float* ray_rgbT, int32_t* nsteps,

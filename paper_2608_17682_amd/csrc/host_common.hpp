@@ -58,6 +58,14 @@ voro_status check_launch(const char* what);
 
 inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
+// stored-exit arguments: a capacity of at least one step, 8-byte alignment
+inline voro_status check_trace(const int32_t* trace, int32_t trace_cap) {
+  if (!trace) return VORO_OK;
+  if (trace_cap < 1) return fail(VORO_EINVAL, "trace_cap = %d: must be >= 1 with a trace", trace_cap);
+  if (!aligned(trace, 8)) return fail(VORO_EINVAL, "trace must be 8-byte aligned");
+  return VORO_OK;
+}
+
 // effective launch parameters after defaults
 struct Launch {
   int lpr, tile_w, tile_h, block;

@@ -141,7 +141,19 @@ struct RayArgs {
   const float* g_dist;   // [R] upstream gradient of the distortion loss (or null)
   Grads g;
   unsigned long long* stats;
+  // stored exits, [trace_cap][n_rays] (null: the adjoint searches every step)
+  int2* trace;
+  int trace_cap;
 };
+
+// the stored exits of one ray (none for a lane without a ray)
+__device__ __forceinline__ ExitTrace ray_exits(const RayArgs& a, int ray) {
+  ExitTrace x;
+  x.p = a.trace && ray >= 0 ? a.trace + ray : nullptr;
+  x.stride = (unsigned)a.map.n_rays;
+  x.cap = a.trace_cap;
+  return x;
+}
 
 // One lane per ray walks with staged edge rows (dynamic LDS:
 // kStageBytesPerWave per wave), also when gathered rows are ranked in half
@@ -176,9 +188,10 @@ __global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
     const RayOut out =
         staged ? walk_forward_staged<TEX, APP, E16>(a.s, a.w, r, ray >= 0, lane,
                                                slabs + wave * (kStageBytesPerWave / 16), rec,
-                                               a.max_record, cnt, a.dist_out != nullptr)
+                                               a.max_record, cnt, a.dist_out != nullptr,
+                                               ray_exits(a, ray))
                : walk_forward<LPR, TEX, APP, E16>(a.s, a.w, r, sub, rec, a.max_record, cnt,
-                                             a.dist_out != nullptr);
+                                             a.dist_out != nullptr, ray_exits(a, ray));
     if (ray >= 0 && sub == 0) {
       a.rgb[3 * (size_t)ray] = out.r;
       a.rgb[3 * (size_t)ray + 1] = out.g;
@@ -260,7 +273,7 @@ __global__ void __launch_bounds__(256)
   // all lanes take part: the gradient records are merged across the wave,
   // then across the workgroup in the LDS table
   walk_backward<LPR, TEX, APP, kCap>(a.s, a.w, r, u, ray >= 0, sub, lane, a.g, &tab, ob, cnt,
-                               a.g_dist != nullptr);
+                               a.g_dist != nullptr, ray_exits(a, ray));
   __syncthreads();
   table_flush(tab, a.g, a.s.res * a.s.res, a.s.res);
   if (a.stats) flush_counters(cnt, sub == 0, lane, a.stats);
@@ -424,11 +437,15 @@ voro_status voro_render_fwd(const voro_scene* scene, const void* ws, size_t ws_b
                             const float* o, const float* d, const float* tmax,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
                             float* rgb, float* T, int32_t* nsteps, int32_t* cells, float* dist,
-                            uint64_t* stats, void* stream) {
+                            int32_t* trace, int32_t trace_cap, uint64_t* stats, void* stream) {
   if (R > 0 && (!rgb || !T)) return fail(VORO_EINVAL, "rgb and T must not be NULL");
   if (params && params->max_record > 0 && !cells)
     return fail(VORO_EINVAL, "cells must not be NULL when max_record > 0");
+  voro_status st0 = check_trace(trace, trace_cap);
+  if (st0 != VORO_OK) return st0;
   RayArgs a = {};
+  a.trace = reinterpret_cast<int2*>(trace);
+  a.trace_cap = trace ? trace_cap : 0;
   a.rgb = rgb;
   a.T = T;
   a.nsteps = nsteps;
@@ -444,8 +461,8 @@ voro_status voro_render_bwd(const voro_scene* scene, void* ws, size_t ws_bytes,
                             const int32_t* start_cell, int32_t R, const voro_params* params,
                             const float* rgb, const float* T, const float* g_rgb,
                             const float* g_T, const float* dist, const float* g_dist,
-                            float* g_sites, float* g_density, float* g_texels, uint64_t* stats,
-                            void* stream) {
+                            const int32_t* trace, int32_t trace_cap, float* g_sites,
+                            float* g_density, float* g_texels, uint64_t* stats, void* stream) {
   if (R > 0 && (!rgb || !T || !g_rgb))
     return fail(VORO_EINVAL, "rgb, T and g_rgb must not be NULL");
   if ((dist == nullptr) != (g_dist == nullptr))
@@ -453,7 +470,11 @@ voro_status voro_render_bwd(const voro_scene* scene, void* ws, size_t ws_bytes,
   if (R > 0 && (!g_sites || !g_density || !g_texels))
     return fail(VORO_EINVAL, "gradient outputs must not be NULL");
   if (g_texels && !aligned(g_texels, 16)) return fail(VORO_EINVAL, "g_texels must be 16-byte aligned");
+  voro_status st0 = check_trace(trace, trace_cap);
+  if (st0 != VORO_OK) return st0;
   RayArgs a = {};
+  a.trace = reinterpret_cast<int2*>(const_cast<int32_t*>(trace));
+  a.trace_cap = trace ? trace_cap : 0;
   a.rgb_in = rgb;
   a.T_in = T;
   a.g_rgb = g_rgb;

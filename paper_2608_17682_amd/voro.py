@@ -102,9 +102,10 @@ def lib():
             "voro_locate_origins": ([P(voro_scene), vp, ctypes.c_size_t, vp, vp, i32, vp, vp, vp],
                                     i32),
             "voro_render_fwd": ([P(voro_scene), vp, ctypes.c_size_t, vp, vp, vp, vp, i32,
-                                 P(voro_params), vp, vp, vp, vp, vp, vp, vp], i32),
+                                 P(voro_params), vp, vp, vp, vp, vp, vp, i32, vp, vp], i32),
             "voro_render_bwd": ([P(voro_scene), vp, ctypes.c_size_t, vp, vp, vp, vp, i32,
-                                 P(voro_params), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+                                 P(voro_params), vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp,
+                                 vp], i32),
             "voro_camera_counts": ([P(voro_camera), i32, P(i64), P(i64)], i32),
             "voro_gen_rays": ([P(voro_camera), i32, vp, vp, vp, vp], i32),
             "voro_render_views_fwd": ([P(voro_scene), vp, ctypes.c_size_t, P(voro_camera), i32,
@@ -332,10 +333,12 @@ def voro_locate_origins(ds: DeviceScene, origins, hint=None, out=None, stats=Non
 
 
 def voro_render_fwd(ds: DeviceScene, o, d, tmax, start, params=None, rgb=None, T=None,
-                    nsteps=None, cells=None, stats=None, stream=None, dist=None):
-    """dist: optional [R,3] float output (distortion loss, sum w sbar, sum w)."""
+                    nsteps=None, cells=None, stats=None, stream=None, dist=None, trace=None):
+    """dist: optional [R,3] float output (distortion loss, sum w sbar, sum w).
+    trace: None, or int32 [cap, R, 2] that receives each ray's first cap exits."""
     import torch
     R = int(o.shape[0])
+    trace, cap = _trace_args(trace, R)
     p = params or default_params()
     dev = o.device
     rgb = torch.empty((R, 3), dtype=torch.float32, device=dev) if rgb is None else rgb
@@ -343,18 +346,20 @@ def voro_render_fwd(ds: DeviceScene, o, d, tmax, start, params=None, rgb=None, T
     sc = ds.c()
     _check(lib().voro_render_fwd(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, _ptr(o), _ptr(d),
                                  _ptr(tmax), _ptr(start), R, ctypes.byref(p), _ptr(rgb), _ptr(T),
-                                 _ptr(nsteps), _ptr(cells), _ptr(dist), _ptr(stats),
-                                 _stream(stream)),
+                                 _ptr(nsteps), _ptr(cells), _ptr(dist), _ptr(trace), cap,
+                                 _ptr(stats), _stream(stream)),
            "voro_render_fwd")
     return rgb, T
 
 
 def voro_render_bwd(ds: DeviceScene, o, d, tmax, start, rgb, T, g_rgb, g_T=None, params=None,
                     g_sites=None, g_density=None, g_texels=None, stats=None, stream=None,
-                    dist=None, g_dist=None):
-    """dist: the forward's [R,3] distortion output, g_dist: [R] its upstream gradient."""
+                    dist=None, g_dist=None, trace=None):
+    """dist: the forward's [R,3] distortion output, g_dist: [R] its upstream gradient;
+    trace: None (every exit searched again) or the forward's stored exits."""
     import torch
     R = int(o.shape[0])
+    trace, cap = _trace_args(trace, R)
     p = params or default_params()
     dev = o.device
     if g_sites is None:
@@ -366,8 +371,9 @@ def voro_render_bwd(ds: DeviceScene, o, d, tmax, start, rgb, T, g_rgb, g_T=None,
     sc = ds.c()
     _check(lib().voro_render_bwd(ctypes.byref(sc), _ptr(ds.ws), ds.ws_bytes, _ptr(o), _ptr(d),
                                  _ptr(tmax), _ptr(start), R, ctypes.byref(p), _ptr(rgb), _ptr(T),
-                                 _ptr(g_rgb), _ptr(g_T), _ptr(dist), _ptr(g_dist), _ptr(g_sites),
-                                 _ptr(g_density), _ptr(g_texels), _ptr(stats), _stream(stream)),
+                                 _ptr(g_rgb), _ptr(g_T), _ptr(dist), _ptr(g_dist), _ptr(trace),
+                                 cap, _ptr(g_sites), _ptr(g_density), _ptr(g_texels),
+                                 _ptr(stats), _stream(stream)),
            "voro_render_bwd")
     return g_sites, g_density, g_texels
 

@@ -109,11 +109,11 @@ def test_render_validation_before_device(L):
     A = 0x300000
     # workspace too small
     st = L.voro_render_fwd(ctypes.byref(s), ws, 16, A, A, A, A, 8, ctypes.byref(p), A, A, None,
-                           None, None, None, None)
+                           None, None, None, 0, None, None)
     assert st == voro.VORO_EWORKSPACE
     # missing ray arrays
     st = L.voro_render_fwd(ctypes.byref(s), ws, n.value, None, A, A, A, 8, ctypes.byref(p), A, A,
-                           None, None, None, None, None)
+                           None, None, None, None, 0, None, None)
     assert st == voro.VORO_EINVAL
     # bad params
     for field, value in [("max_steps", 0), ("lanes_per_ray", 3), ("block", 100),
@@ -121,47 +121,47 @@ def test_render_validation_before_device(L):
                          ("appearance", 3)]:
         q = voro.default_params(**{field: value})
         st = L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
-                               None, None, None, None, None)
+                               None, None, None, None, 0, None, None)
         assert st in (voro.VORO_EINVAL, voro.VORO_EUNSUPPORTED), field
     q = voro.default_params(appearance=3)
     assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
-                             None, None, None, None, None) == voro.VORO_EUNSUPPORTED
+                             None, None, None, None, 0, None, None) == voro.VORO_EUNSUPPORTED
     # the spherical-harmonic comparison model is forward only and needs its
     # coefficient layout
     q = voro.default_params(appearance=2)
     assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
-                             None, None, None, None, None) == voro.VORO_EINVAL
+                             None, None, None, None, 0, None, None) == voro.VORO_EINVAL
     assert "spherical-harmonic" in voro.last_error()
     assert L.voro_render_bwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A, A,
-                             None, None, None, A, A, A, None, None) == voro.VORO_EUNSUPPORTED
+                             None, None, None, None, 0, A, A, A, None, None) == voro.VORO_EUNSUPPORTED
     # the full appearance model needs two maps per cell, and the single-map
     # model one
     q = voro.default_params(appearance=1)
     assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
-                             None, None, None, None, None) == voro.VORO_EINVAL
+                             None, None, None, None, 0, None, None) == voro.VORO_EINVAL
     assert "two texture maps" in voro.last_error()
     s2 = voro.voro_scene.from_buffer_copy(s)
     s2.tex_maps = 2
     n2 = ctypes.c_size_t()
     assert L.voro_workspace_size(ctypes.byref(s2), ctypes.byref(n2)) == 0
     assert L.voro_render_fwd(ctypes.byref(s2), ws, n2.value, A, A, A, A, 8, ctypes.byref(p), A, A,
-                             None, None, None, None, None) == voro.VORO_EINVAL
+                             None, None, None, None, 0, None, None) == voro.VORO_EINVAL
     assert "one texture map" in voro.last_error()
     q = voro.default_params(tile_w=8, tile_h=4)  # 8*4*1 != 64
     assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A,
-                             None, None, None, None, None) == voro.VORO_EINVAL
+                             None, None, None, None, 0, None, None) == voro.VORO_EINVAL
     # backward refuses skip_w != 0
     q = voro.default_params(skip_w=1e-3)
     st = L.voro_render_bwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(q), A, A, A,
-                           None, None, None, A, A, A, None, None)
+                           None, None, None, None, 0, A, A, A, None, None)
     assert st == voro.VORO_EINVAL and "skip_w" in voro.last_error()
     # the distortion loss's saved totals and its upstream gradient come together
     st = L.voro_render_bwd(ctypes.byref(s), ws, n.value, A, A, A, A, 8, ctypes.byref(p), A, A, A,
-                           None, A, None, A, A, A, None, None)
+                           None, A, None, None, 0, A, A, A, None, None)
     assert st == voro.VORO_EINVAL and "g_dist" in voro.last_error()
     # R == 0 is a no-op even without a device
     assert L.voro_render_fwd(ctypes.byref(s), ws, n.value, None, None, None, None, 0,
-                             ctypes.byref(p), None, None, None, None, None, None, None) == 0
+                             ctypes.byref(p), None, None, None, None, None, None, 0, None, None) == 0
 
 
 def test_valid_call_without_device_is_enodev(L):

@@ -137,15 +137,18 @@ def test_config3_sequences_and_colours(dev, c3):
     check_sequences(c3.ds, c3.perm, c3.inv, c3.g, dev, c3.pf, "config3")
 
 
-def test_config3_adjoint_sampled_rays(dev, c3):
-    announce("config3: adjoint of the non-degenerate sampled rays (explicit rays)")
+@pytest.mark.parametrize("cap", [0, 256])
+def test_config3_adjoint_sampled_rays(dev, c3, cap):
+    announce(f"config3: adjoint of the non-degenerate sampled rays (explicit rays, stored exits "
+             f"{cap})")
     g = c3.g
     sel = ~g["degenerate"]
     O, D, TM = (to_dev(g[k][sel], dev) for k in ("o", "d", "tmax"))
     S = to_dev(c3.inv[g["start"][sel]].astype(np.int32), dev)
-    rgb, T = voro.voro_render_fwd(c3.ds, O, D, TM, S, c3.pf)
+    trace = torch.empty((cap, O.shape[0], 2), dtype=torch.int32, device=dev) if cap else None
+    rgb, T = voro.voro_render_fwd(c3.ds, O, D, TM, S, c3.pf, trace=trace)
     gs, gd, gt = voro.voro_render_bwd(c3.ds, O, D, TM, S, rgb, T, to_dev(g["g_rgb"][sel], dev),
-                                      None, c3.pb)
+                                      None, c3.pb, trace=trace)
     assert_grads_match(g, gs.cpu().numpy(), gd.cpu().numpy(), gt.cpu().numpy(), c3.inv,
                        "config3 explicit")
 

@@ -435,6 +435,30 @@ def test_views_stored_exits(dev, c1, lpr, schedule, cap):
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(a).max()), name
 
 
+@pytest.mark.parametrize("lpr", [1, 4])
+def test_explicit_stored_exits_are_the_walk(dev, c1, lpr):
+    # explicit rays: the stored exits lead from each visited cell to the next
+    # one, and storing them changes no forward output
+    R = c1.O.shape[0]
+    cap = 5
+    p = voro.default_params(lanes_per_ray=lpr)
+    p.max_record = 256
+    announce(f"explicit rays: stored exits lpr={lpr}")
+    K = torch.empty(R, dtype=torch.int32, device=dev)
+    cells = torch.empty((R, 256), dtype=torch.int32, device=dev)
+    rgb0, T0 = voro.voro_render_fwd(c1.ds, c1.O, c1.D, c1.TM, c1.S, p, nsteps=K, cells=cells)
+    trace = torch.full((cap, R, 2), -7, dtype=torch.int32, device=dev)
+    rgb1, T1 = voro.voro_render_fwd(c1.ds, c1.O, c1.D, c1.TM, c1.S, voro.default_params(
+        lanes_per_ray=lpr), trace=trace)
+    assert torch.equal(rgb0, rgb1) and torch.equal(T0, T1)
+    K, cells, tr = K.cpu().numpy(), cells.cpu().numpy(), trace.cpu().numpy()
+    assert K.max() <= 256 and (K > cap).any()
+    for i in range(R):
+        m = min(int(K[i]), cap)
+        assert np.array_equal(tr[:max(m - 1, 0), i, 1], cells[i, 1:max(m, 1)]), i
+        assert (tr[m:, i] == -7).all(), i
+
+
 def test_views_stored_exit_outside_the_scene_ends_the_ray(dev, c1):
     # A stored next cell outside [0, n) (a buffer from another walk) is never
     # read: the adjoint ends that ray's walk there, so every ray here stops
@@ -485,8 +509,9 @@ def test_distortion_fwd_matches_oracle(dev, c1):
     assert torch.equal(rgb, rgb0)
 
 
+@pytest.mark.parametrize("cap", [0, 3])
 @pytest.mark.parametrize("lpr", [1, 4])
-def test_distortion_bwd_matches_oracle_gradient(dev, c1, lpr):
+def test_distortion_bwd_matches_oracle_gradient(dev, c1, lpr, cap):
     deg = np.array([degenerate(r, 1e-4, float(c1.tm[0])) for r in c1.recs])
     sel = np.nonzero(~deg)[0]
     g_rgb, g_T = synth.upstream(len(c1.o), 1)
@@ -494,26 +519,31 @@ def test_distortion_bwd_matches_oracle_gradient(dev, c1, lpr):
     g_dist = np.random.default_rng(17).normal(0.0, 3.0, len(sel)).astype(np.float32)
     want = adjoint.grad_rays(c1.scene.sites, c1.scene.density, c1.scene.texels, c1.o[sel],
                              c1.d[sel], c1.tm[sel], [c1.recs[i] for i in sel], g_rgb, g_T, g_dist)
-    announce(f"distortion bwd config1 lpr={lpr}")
+    announce(f"distortion bwd config1 lpr={lpr} stored exits {cap}")
     si = torch.from_numpy(sel).to(dev)
     p = voro.default_params(lanes_per_ray=lpr)
     dist = torch.empty((len(sel), 3), dtype=torch.float32, device=dev)
-    rgb, T = voro.voro_render_fwd(c1.ds, c1.O[si], c1.D[si], c1.TM[si], c1.S[si], p, dist=dist)
+    # cap 3: each ray's first three exits are read from the forward's store,
+    # the later ones searched
+    trace = torch.empty((cap, len(sel), 2), dtype=torch.int32, device=dev) if cap else None
+    rgb, T = voro.voro_render_fwd(c1.ds, c1.O[si], c1.D[si], c1.TM[si], c1.S[si], p, dist=dist,
+                                  trace=trace)
     got = voro.voro_render_bwd(c1.ds, c1.O[si], c1.D[si], c1.TM[si], c1.S[si], rgb, T,
                                to_dev(g_rgb, dev), to_dev(g_T, dev), p, dist=dist,
-                               g_dist=to_dev(g_dist, dev))
+                               g_dist=to_dev(g_dist, dev), trace=trace)
     for g, w, name in zip(got, want, ("sites", "density", "texels")):
         assert_grad_close(g.cpu().numpy(), w, name)
 
 
-def test_autograd_distortion(dev, c1):
+@pytest.mark.parametrize("stored_exits", [0, 64])
+def test_autograd_distortion(dev, c1, stored_exits):
     from paper_2608_17682_amd.autograd import render as vrender
     sites = c1.ds.sites.clone().requires_grad_(True)
     rho = torch.log(c1.ds.density.clone()).requires_grad_(True)
     tex = c1.ds.texels.clone().requires_grad_(True)
-    announce("autograd render with distortion")
+    announce(f"autograd render with distortion, stored exits {stored_exits}")
     rgb, T, ld = vrender(sites, torch.exp(rho), tex, c1.ds.nbr_off, c1.ds.nbr_idx, c1.O, c1.D,
-                         c1.TM, c1.S, distortion=True)
+                         c1.TM, c1.S, distortion=True, stored_exits=stored_exits)
     lam = 0.37
     (rgb.sum() + lam * ld.sum()).backward()
     deg = np.array([degenerate(r, 1e-4, float(c1.tm[0])) for r in c1.recs])
