@@ -327,8 +327,9 @@ __global__ void __launch_bounds__(256) k_views_fwd_refill(ViewsArgs a) {
 // wide), walked by the whole workgroup into one LDS gradient table that is
 // flushed to global memory before the next unit.  The persistent
 // one-lane-per-ray single-map adjoint is held to 128 VGPRs and a 528-entry
-// table, four workgroups of four waves per CU instead of three (its few
-// spills sit outside the walk loop); the other forms keep the larger table.
+// table, four workgroups of four waves per CU instead of three (it spills
+// 84 bytes per lane, a few of whose reloads fall inside the walk loop; the
+// extra wave still wins); the other forms keep the larger table.
 template <int LPR, int APP, bool PERSIST>
 struct BwdShape {
   static constexpr bool quad = PERSIST && LPR == 1 && APP == 0;

@@ -157,9 +157,18 @@ __device__ __forceinline__ ExitTrace ray_exits(const RayArgs& a, int ray) {
 
 // One lane per ray walks with staged edge rows (dynamic LDS:
 // kStageBytesPerWave per wave), also when gathered rows are ranked in half
-// precision.
+// precision.  The one-lane-per-ray exact single-map walk is held to five
+// waves per SIMD (96 VGPRs), as in the multi-view forward: the stored-exit
+// arguments would otherwise take it to 98 and four waves.
+template <int LPR, int APP, bool E16>
+struct RenderFwdWaves {
+  static constexpr int value = (LPR == 1 && APP == 0 && !E16) ? 5 : 1;
+};
+
 template <int LPR, int TEX, int APP, bool E16>
-__global__ void __launch_bounds__(256) k_render_fwd(RayArgs a) {
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(RenderFwdWaves<LPR, APP, E16>::value, 8)))
+    k_render_fwd(RayArgs a) {
   extern __shared__ float4 slabs[];
   const int nwaves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
