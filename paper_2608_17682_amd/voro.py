@@ -399,6 +399,8 @@ def _trace_args(trace, nr):
             or trace.shape[2] != 2 or not trace.is_contiguous()):
         raise ValueError(f"trace must be a contiguous int32 tensor [cap, {nr}, 2], got "
                          f"{trace.dtype} {tuple(trace.shape)}")
+    if not trace.is_cuda:
+        raise ValueError("trace must be device memory (the kernels write and read it)")
     return trace, int(trace.shape[0])
 
 

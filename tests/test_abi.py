@@ -213,8 +213,9 @@ def test_views_trace_validation(L):
         voro._trace_args(torch.zeros((4, 7, 2), dtype=torch.int64), 7)
     with pytest.raises(ValueError):
         voro._trace_args(torch.zeros((4, 6, 2), dtype=torch.int32), 7)
-    t = torch.zeros((4, 7, 2), dtype=torch.int32)
-    assert voro._trace_args(t, 7)[1] == 4 and voro._trace_args(None, 7) == (None, 0)
+    with pytest.raises(ValueError, match="device memory"):
+        voro._trace_args(torch.zeros((4, 7, 2), dtype=torch.int32), 7)
+    assert voro._trace_args(None, 7) == (None, 0)
 
 
 def test_cast_and_reorder_validation(L):
