@@ -445,7 +445,8 @@ __device__ __forceinline__ RayOut walk_forward_staged(const DevScene& s, const W
 // ------------------------------------------------------------- adjoint
 //
 // Adjoint of walk_forward for L = g.C + g_T T_final.  The walk is replayed
-// with identical decisions and, per segment k (App. X of the derivation in
+// with identical decisions (each exit searched again, or read from the
+// forward's stored exits) and, per segment k (App. X of the derivation in
 // the oracle's adjoint module):
 //   dL/dtau_k  = g.(T_{k+1} c_k - S_k) - g_T T_final,  S_k = C - sum_{j<=k} w_j c_j
 //   dL/dsigma  += dL/dtau_k delta_k,    dL/dtexel_q += w_k b_q g
