@@ -52,3 +52,15 @@ def test_gradients_refuse_forward_only_variants(field, value):
     st = torch.zeros(2, dtype=torch.int32)
     with pytest.raises(ValueError, match=field):
         render(sites, dens, tex, off, idx, o, d, tm, st, p)
+
+
+def test_stored_exits_must_not_be_negative():
+    sites, dens, tex, off, idx, cam = _args()
+    with pytest.raises(ValueError, match="stored_exits"):
+        render_views(sites, dens, tex, off, idx, [cam], stored_exits=-1)
+    o = torch.zeros((2, 3))
+    d = torch.zeros((2, 3))
+    tm = torch.ones(2)
+    st = torch.zeros(2, dtype=torch.int32)
+    with pytest.raises(ValueError, match="stored_exits"):
+        render(sites, dens, tex, off, idx, o, d, tm, st, stored_exits=-1)
