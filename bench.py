@@ -226,8 +226,8 @@ def roofline_of(counters, ms, algo_bytes, kernel):
     """Roofline entry of one kernel.  The binding roof is the most used of:
     HBM (calibrated FETCH_SIZE + WRITE_SIZE per launch over the live launch
     time, against 8 TB/s), VALU issue (wave instructions per launch over the
-    chip's 614.4 G/s) and the texture address / data units (busy cycles over
-    the kernel's cycles, per CU, from the profile run).  The byte model's
+    chip's 614.4 G/s), the texture address / data units and the LDS (busy
+    cycles over the kernel's cycles, per CU, from the profile run).  The byte model's
     bytes over the same live time are reported as `effective`, never as
     `frac`."""
     s = ms * 1e-3
@@ -703,7 +703,8 @@ def summarise_counters(out_path, kernel, dirs, copy_dirs):
         cyc = k["GRBM_GUI_ACTIVE"][0] / 8.0      # summed over the 8 XCDs
         out["cycles_per_launch"] = cyc
         busy = {}
-        for name, key in (("texture_addr", "TA_TA_BUSY_sum"), ("texture_data", "TD_TD_BUSY_sum")):
+        for name, key in (("texture_addr", "TA_TA_BUSY_sum"), ("texture_data", "TD_TD_BUSY_sum"),
+                          ("lds", "SQ_LDS_IDX_ACTIVE")):
             if key in k:
                 busy[name] = round(k[key][0] / 256.0 / cyc, 4)
         if busy:

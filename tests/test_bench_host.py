@@ -46,6 +46,9 @@ def test_roofline_takes_the_most_used_roof():
     # the byte model only ever appears as the labelled effective figure
     assert r["effective"]["gbs"] == pytest.approx(8000.0)
     assert r["effective"]["frac_of_hbm_peak"] == pytest.approx(1.0)
+    # the LDS busier than every other unit
+    r = bench.roofline_of(_counters(1e9, 0.1e9, {"texture_data": 0.5, "lds": 0.7}), ms, 8e9, "k")
+    assert r["bound"] == "lds" and r["frac"] == 0.7
     # VALU issue: 0.5 G wave instructions in 1 ms against 614.4 G/s
     r = bench.roofline_of(_counters(1e9, 0.5e9, {"texture_data": 0.2}), ms, 8e9, "k")
     assert r["bound"] == "alu" and r["frac"] == pytest.approx(0.5 / 0.6144, rel=1e-3)
