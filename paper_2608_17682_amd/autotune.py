@@ -4,7 +4,9 @@ Picks, per workload class and direction (forward / adjoint), the number of
 lanes that share a ray's neighbour tests (rays per wave = 64 / lanes), the
 screen tile a wave walks, the workgroup size and the schedule (grid,
 persistent queue or lane refill), by timing the multi-view launch with HIP
-events on the caller's device.
+events on the caller's device.  The forward is timed as an inference pass
+runs it; the adjoint reads the exits the forward stored (STORED_EXITS steps
+per ray), as a training step does.
 
 A workload class is keyed by what changes the best launch: the scene size
 (rounded up to a power of two), the texture resolution, the texel storage
@@ -124,6 +126,10 @@ def _time(fn, reps: int, warmup: int = 1) -> float:
     return e0.elapsed_time(e1) / reps
 
 
+# steps per ray of the stored exits the adjoint is timed with
+STORED_EXITS = 256
+
+
 def tune(ds, cams, reps: int = 3, cands: Iterable[dict] = None, log=print) -> Dict[str, dict]:
     """Time every candidate on the multi-view launch over `cams` (prepared
     DeviceScene `ds`); returns {'fwd': best, 'bwd': best} with times in ms."""
@@ -141,7 +147,8 @@ def tune(ds, cams, reps: int = 3, cands: Iterable[dict] = None, log=print) -> Di
     gd = torch.zeros(ds.n, device=dev)
     gt = torch.zeros(tuple(ds.texels.shape), device=dev)
     base = voro.default_params()
-    voro.voro_render_views_fwd(ds, arr, base, rgb, T, ray)
+    trace = torch.empty((STORED_EXITS, nr, 2), dtype=torch.int32, device=dev)
+    voro.voro_render_views_fwd(ds, arr, base, rgb, T, ray, trace=trace)
     best = {}
     for direction in ("fwd", "bwd"):
         res = []
@@ -153,7 +160,7 @@ def tune(ds, cams, reps: int = 3, cands: Iterable[dict] = None, log=print) -> Di
                 fn = lambda: voro.voro_render_views_fwd(ds, arr, p, rgb, T, ray)  # noqa: E731
             else:
                 fn = lambda: voro.voro_render_views_bwd(ds, arr, rgb, T, ray, g, None, p,  # noqa
-                                                        gs, gd, gt)
+                                                        gs, gd, gt, trace=trace)
             ms = _time(fn, reps)
             res.append((ms, c))
         res.sort(key=lambda x: x[0])
@@ -162,6 +169,8 @@ def tune(ds, cams, reps: int = 3, cands: Iterable[dict] = None, log=print) -> Di
                           and cc["block"] == 256 and cc["schedule"] == 1)
         best[direction] = dict(c, ms=round(ms, 4), default_ms=round(default_ms, 4),
                                rays=int(nr), candidates=len(res))
+        if direction == "bwd":
+            best[direction]["stored_exits"] = STORED_EXITS
         log(f"[autotune] {direction}: best {c} {ms:.3f} ms (default 1x8x8/256: {default_ms:.3f} ms)")
     return best
 
